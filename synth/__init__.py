@@ -1,0 +1,242 @@
+"""Seeded synthetic inputs for the clustering hot path.
+
+This module only draws points and turns them into distance matrices.  It holds
+none of the clustering arithmetic, and both the CPU oracle (test side) and the
+GPU library (product side) consume what it produces.
+
+Every matrix is fp32, n x n, row-major, zero diagonal.  Only the strict upper
+triangle is meaningful to the algorithm (Section 5.2: a distance matrix needs
+only its upper or lower half); the lower triangle produced here is the mirror
+up to rounding of the Gram-matrix formula and is ignored by every consumer.
+
+Workload recipes follow the paper's setting (Section 6: complete linkage on
+protein-structure RMSD matrices, average n about 1968) with synthetic
+Gaussian-mixture points standing in for the protein data, which is not
+available.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+BASE_SEED = 170906816
+
+LINKAGES = ("single", "complete", "average", "ward")
+
+
+def _torch():
+    import torch  # CPU only: used for multi-threaded fp64 block arithmetic
+
+    return torch
+
+
+def gaussian_mixture(rng: np.random.Generator, n: int, dim: int, k: int,
+                     sigma_lo: float = 1.0, sigma_hi: float = 1.0,
+                     anisotropic: bool = False, box: float = 10.0) -> np.ndarray:
+    """Draw n points in R^dim from a mixture of k Gaussians (float64).
+
+    Centres ~ U[-box, box]^dim, labels uniform over clusters.  Isotropic
+    clusters use one sigma per cluster ~ U[sigma_lo, sigma_hi]; anisotropic
+    clusters use x = c + R diag(s) z with R a random orthogonal matrix (QR of a
+    Gaussian) and s_d ~ U[0.3, 3].
+    """
+    centres = rng.uniform(-box, box, size=(k, dim))
+    labels = rng.integers(0, k, size=n)
+    z = rng.standard_normal((n, dim))
+    if not anisotropic:
+        sig = rng.uniform(sigma_lo, sigma_hi, size=k)
+        return centres[labels] + z * sig[labels, None]
+    pts = np.empty((n, dim))
+    for c in range(k):
+        q, r = np.linalg.qr(rng.standard_normal((dim, dim)))
+        q = q * np.sign(np.diag(r))[None, :]
+        s = rng.uniform(0.3, 3.0, size=dim)
+        sel = labels == c
+        pts[sel] = centres[c] + (z[sel] * s[None, :]) @ q.T
+    return pts
+
+
+def euclidean_matrix(points: np.ndarray, scale_to: float | None = None,
+                     round_decimals: int | None = None, out: np.ndarray | None = None,
+                     block: int = 2048) -> np.ndarray:
+    """Full n x n fp32 Euclidean distance matrix of float64 points.
+
+    Distances are sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) evaluated in float64
+    block by block, optionally rescaled so the largest distance equals
+    ``scale_to`` and rounded (half to even) to ``round_decimals`` decimals,
+    then rounded once to fp32.  The diagonal is exactly zero.
+    """
+    torch = _torch()
+    x = torch.from_numpy(np.ascontiguousarray(points, dtype=np.float64))
+    n = x.shape[0]
+    sq = (x * x).sum(1)
+    if out is None:
+        out = np.empty((n, n), dtype=np.float32)
+    out_t = torch.from_numpy(out)
+    buf = torch.empty((min(block, n), n), dtype=torch.float64)
+
+    def fill(r0, r1):
+        b = buf[: r1 - r0]
+        torch.matmul(x[r0:r1], x.T, out=b)
+        b.mul_(-2.0).add_(sq[r0:r1, None]).add_(sq[None, :]).clamp_min_(0.0).sqrt_()
+        return b
+
+    factor = None
+    if scale_to is not None:
+        dmax = 0.0
+        for r0 in range(0, n, block):
+            dmax = max(dmax, float(fill(r0, min(n, r0 + block)).max()))
+        factor = scale_to / dmax if dmax > 0 else 1.0
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        b = fill(r0, r1)
+        if factor is not None:
+            b.mul_(factor)
+        if round_decimals is not None:
+            p = 10.0 ** round_decimals
+            b.mul_(p).round_().div_(p)
+        out_t[r0:r1].copy_(b)
+    idx = np.arange(n)
+    out[idx, idx] = 0.0
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def mixture_512(seed: int = BASE_SEED + 1) -> np.ndarray:
+    """n=512 points in R^8, 8 isotropic clusters, sigma=1."""
+    rng = np.random.default_rng(seed)
+    return euclidean_matrix(gaussian_mixture(rng, 512, 8, 8))
+
+
+def mixture_8192(seed: int = BASE_SEED + 2, n: int = 8192) -> np.ndarray:
+    """n=8192 points in R^16, 32 clusters with sigma ~ U[0.5, 2]."""
+    rng = np.random.default_rng(seed)
+    return euclidean_matrix(gaussian_mixture(rng, n, 16, 32, 0.5, 2.0))
+
+
+def rmsd_like(seed: int = BASE_SEED + 3, n: int = 32768, out: np.ndarray | None = None) -> np.ndarray:
+    """RMSD-like matrix: n points in R^30 from 64 anisotropic clusters,
+    distances rescaled to [0, 20] and rounded to 1e-3 (many exact ties)."""
+    rng = np.random.default_rng(seed)
+    pts = gaussian_mixture(rng, n, 30, 64, anisotropic=True)
+    return euclidean_matrix(pts, scale_to=20.0, round_decimals=3, out=out)
+
+
+def log_uniform_int(rng: np.random.Generator, lo: int, hi: int, size=None):
+    return np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi), size=size))).astype(np.int64)
+
+
+@dataclass
+class BatchSpec:
+    ns: np.ndarray          # int64[count]
+    linkages: np.ndarray    # int32[count], 0..3
+    seeds: np.ndarray       # int64[count]
+
+
+def batch_spec(count: int = 1024, n_lo: int = 64, n_hi: int = 4096,
+               seed: int = BASE_SEED + 4) -> BatchSpec:
+    """Ragged batch: n log-uniform in [n_lo, n_hi], linkage uniform over 4."""
+    rng = np.random.default_rng(seed)
+    ns = np.minimum(log_uniform_int(rng, n_lo, n_hi, size=count), n_hi)
+    links = rng.integers(0, 4, size=count).astype(np.int32)
+    seeds = seed * 1000 + np.arange(count, dtype=np.int64)
+    return BatchSpec(ns, links, seeds)
+
+
+def batch_instance(n: int, seed: int) -> np.ndarray:
+    """One batch instance: Gaussian mixture in R^16, K ~ U{2..32} clusters,
+    sigma ~ U[0.5, 2]."""
+    rng = np.random.default_rng(int(seed))
+    k = int(rng.integers(2, 33))
+    return euclidean_matrix(gaussian_mixture(rng, int(n), 16, k, 0.5, 2.0))
+
+
+def pack_offsets(ns, align: int = 64):
+    """Element offsets of n_k x n_k blocks packed back to back, each start
+    aligned to ``align`` floats.  Returns (offsets int64[count], total)."""
+    offs = np.empty(len(ns), dtype=np.int64)
+    cur = 0
+    for k, n in enumerate(ns):
+        cur = (cur + align - 1) // align * align
+        offs[k] = cur
+        cur += int(n) * int(n)
+    return offs, (cur + align - 1) // align * align
+
+
+def merge_offsets(ns):
+    """Merge-record offsets: instance k's n_k - 1 records start at
+    sum_{l<k} (n_l - 1)."""
+    ns = np.asarray(ns, dtype=np.int64)
+    m = np.maximum(ns - 1, 0)
+    offs = np.zeros(len(ns), dtype=np.int64)
+    if len(ns) > 1:
+        offs[1:] = np.cumsum(m)[:-1]
+    return offs, int(m.sum())
+
+
+@dataclass
+class ServeTrace:
+    arrivals: np.ndarray    # float64 seconds, increasing
+    ns: np.ndarray
+    linkages: np.ndarray
+    seeds: np.ndarray
+
+
+def serve_trace(count: int, rate: float = 200.0, n_lo: int = 256, n_hi: int = 16384,
+                seed: int = BASE_SEED + 5) -> ServeTrace:
+    """Poisson arrivals at ``rate`` per second; n log-uniform on [n_lo, n_hi];
+    linkage uniform over the four."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    ns = np.minimum(log_uniform_int(rng, n_lo, n_hi, size=count), n_hi)
+    links = rng.integers(0, 4, size=count).astype(np.int32)
+    seeds = seed * 1000 + np.arange(count, dtype=np.int64)
+    return ServeTrace(np.cumsum(gaps), ns, links, seeds)
+
+
+# ---------------------------------------------------------------------------
+# Small structured matrices for edge cases
+# ---------------------------------------------------------------------------
+
+def uniform_matrix(n: int, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """Independent U[lo, hi) entries (not a metric), zero diagonal, symmetric."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(lo, hi, size=(n, n)).astype(np.float32)
+    a = np.triu(a, 1)
+    return a + a.T
+
+
+def quantized_matrix(n: int, seed: int, levels: int = 7) -> np.ndarray:
+    """Entries drawn from a handful of values: tie-heavy."""
+    rng = np.random.default_rng(seed)
+    a = rng.integers(1, levels + 1, size=(n, n)).astype(np.float32) * 0.5
+    a = np.triu(a, 1)
+    return a + a.T
+
+
+def ultrametric_matrix(n: int, seed: int) -> np.ndarray:
+    """Ultrametric from a random binary hierarchy with distinct levels:
+    D[a][b] = level of the lowest common ancestor of leaves a and b."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    d = np.zeros((n, n), dtype=np.float64)
+    levels = iter(np.sort(rng.uniform(1.0, 100.0, size=max(1, n - 1)))[::-1])
+
+    def split(items):
+        if len(items) <= 1:
+            return
+        cut = int(rng.integers(1, len(items)))
+        left, right = items[:cut], items[cut:]
+        lev = next(levels)
+        d[np.ix_(left, right)] = lev
+        d[np.ix_(right, left)] = lev
+        split(left)
+        split(right)
+
+    split(list(perm))
+    return d.astype(np.float32)
