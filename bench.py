@@ -1,0 +1,240 @@
+"""Benchmark: full dendrogram of the n=32768 RMSD-like complete-linkage
+workload on one MI355X, plus the batched workload against a per-instance
+launch loop, plus the CPU oracle on a bounded sample.
+
+Prints one JSON line.  A step is one hac_run over the whole n=32768 instance
+(set-up, all 32767 merges, merge list back in device memory) with the input
+already resident in HBM; HAC_PRESERVE_INPUT makes each step start from the
+same input (the 4 GiB device-to-device copy is inside the timed step).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batch] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "HBM GB/s & dendrogram s at n=32768; batched instances/s vs per-instance loop"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_run(n, st):
+    """Algorithmic HBM bytes of one hac_run launch:
+    set-up reads the strict upper triangle and writes its mirror (4 bytes
+    each way per off-diagonal pair: 4 n(n-1) bytes); each Lance-Williams
+    update of an entry reads D[i][k], D[j][k] and writes D[i][k], D[k][i]
+    (16 bytes); each rescan reads one fp32 per live entry it visits; each
+    merge writes a 16-byte record."""
+    return (4.0 * n * (n - 1) + 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"]
+            + 16.0 * (n - 1))
+
+
+def cpu_baseline(d, link, n, budget_s, gpu_prefix):
+    """Time the oracle (unchanged) on the first K merges of the same input,
+    K grown until the sample takes a few seconds of the budget, and
+    extrapolate to the whole dendrogram by the number of cells its scan
+    visits: merge s scans m(m-1)/2 cells with m = n - s live clusters."""
+    import oracle
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    oracle.run_f32(d, link, max_merges=0, threads=threads)
+    t_setup = time.perf_counter() - t0
+    k = 4
+    t_k = None
+    res = None
+    while True:
+        t0 = time.perf_counter()
+        res = oracle.run_f32(d, link, max_merges=k, threads=threads)
+        t_k = time.perf_counter() - t0
+        if t_k - t_setup > budget_s / 3 or k >= n - 1:
+            break
+        k *= 2
+    m = np.arange(2, n + 1, dtype=np.float64)
+    cells_all = float(np.sum(m * (m - 1) / 2))
+    ms = np.arange(n - k + 1, n + 1, dtype=np.float64)
+    cells_k = float(np.sum(ms * (ms - 1) / 2))
+    per_cell = max(t_k - t_setup, 1e-9) / cells_k
+    t_full = t_setup + per_cell * cells_all
+    prefix_ok = bool(res.tobytes() == gpu_prefix[:len(res)].tobytes())
+    return {
+        "value": 1.0 / t_full, "unit": "dendrograms/s", "cores": threads, "kind": "oracle",
+        "sample": "first %d of %d merges of the same n=%d input (%.1f s incl. %.1f s set-up); "
+                  "whole dendrogram extrapolated by scanned cells: %.0f s" % (k, n - 1, n, t_k, t_setup, t_full),
+        "est_dendrogram_s": t_full,
+        "parity_prefix_merges": int(len(res)),
+        "parity_prefix_ok": prefix_ok,
+    }
+
+
+def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
+    import synth
+    spec = synth.batch_spec(count=count, n_lo=n_lo, n_hi=n_hi)
+    offs, total = synth.pack_offsets(spec.ns)
+    log("batch: generating %d instances (%.2f GB)" % (count, total * 4 / 1e9))
+    host = np.empty(total, np.float32)
+    for k, (n, s) in enumerate(zip(spec.ns, spec.seeds)):
+        host[offs[k]:offs[k] + int(n) * int(n)] = synth.batch_instance(int(n), int(s)).ravel()
+    src = torch.from_numpy(host).cuda()
+    del host
+    work = torch.empty_like(src)
+    moff, mtot = synth.merge_offsets(spec.ns)
+    out_b = torch.empty(mtot * 16, dtype=torch.uint8, device="cuda")
+    out_l = torch.empty(mtot * 16, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def one_batch():
+        work.copy_(src)
+        ctx.batch(work, offs, spec.ns, spec.linkages, out=out_b)
+        ctx.sync()
+
+    def one_loop():
+        work.copy_(src)
+        base = work.data_ptr()
+        obase = out_l.data_ptr()
+        for k in range(count):
+            n = int(spec.ns[k])
+            ctx.run_ptr(base + 4 * int(offs[k]), n, int(spec.linkages[k]),
+                        out=obase + 16 * int(moff[k]))
+        ctx.sync()
+
+    one_batch()
+    torch.cuda.synchronize()
+    tb = []
+    kb = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one_batch()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        kb.append(ctx.stats()["kernel_ms"])
+    log("batch: per-instance loop")
+    one_loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one_loop()
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    same = bool(torch.equal(out_b, out_l))
+    tbm = float(np.median(tb))
+    return {
+        "workload": "%d instances, n log-uniform in [%d, %d], linkage uniform over 4, "
+                    "Gaussian mixtures in R^16, packed ragged (%.2f GB)" % (count, n_lo, n_hi, total * 4 / 1e9),
+        "instances_per_s": count / tbm,
+        "batch_s": tbm,
+        "batch_kernel_ms": float(np.median(kb)),
+        "loop_instances_per_s": count / tl,
+        "loop_s": tl,
+        "speedup_vs_loop": tl / tbm,
+        "identical_to_loop": same,
+        "merges": int(mtot),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--workgroups", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1709_06816_amd as hac
+    import synth
+
+    n = args.n
+    link = "complete"
+    seed = synth.BASE_SEED + 3
+    log("generating rmsd_like n=%d" % n)
+    d = synth.rmsd_like(seed=seed, n=n)
+    src = torch.from_numpy(d).cuda()
+    ctx = hac.Context(0)
+    if args.workgroups:
+        ctx.set_option(hac.OPT_WORKGROUPS, args.workgroups)
+    out = torch.empty((n - 1) * 16, dtype=torch.uint8, device="cuda")
+
+    def step():
+        ctx.run(src, link, preserve=True, out=out)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+        ctx.sync()
+    torch.cuda.synchronize()
+    kms, stats = [], None
+    log("timing %d steps" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        ctx.sync()
+        stats = ctx.stats()
+        kms.append(stats["kernel_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed * 1000.0 / args.steps
+    merges = np.frombuffer(out.cpu().numpy().tobytes(), dtype=hac.MERGE_DTYPE)
+    kernel_ms = float(np.mean(kms))
+    ab = alg_bytes_run(n, stats)
+    achieved = ab / (kernel_ms / 1000.0) / 1e9
+    log("step %.1f ms, merge kernel %.1f ms, %d workgroups" % (ms_step, kernel_ms, stats["workgroups"]))
+
+    result = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_step,
+        "unit": "dendrograms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rmsd_like n=%d complete linkage (R^30, 64 anisotropic clusters, "
+                               "distances scaled to [0,20] and rounded to 1e-3)" % n,
+                   "n": n, "linkage": link, "seed": seed, "parallelism": "1 GPU"},
+        "dendrogram_s": ms_step / 1000.0,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_run (persistent merge kernel)", "kernel_ms": kernel_ms,
+            "alg_bytes_per_launch": ab, "workgroups": stats["workgroups"],
+            "rescans": stats["rescans"], "rescan_elems": stats["rescan_elems"],
+            "update_elems": stats["update_elems"],
+            "note": "latency-bound: one grid-wide exchange per merge",
+        },
+    }
+    if not args.no_batch:
+        log("batch leg")
+        result["batched"] = batch_leg(torch, hac, ctx, args.batch_count, 64, 4096, reps=3)
+    if not args.no_cpu:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(d, link, n, args.cpu_budget, merges)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * hac.h -- Lance-Williams agglomerative clustering on one MI355X (gfx950).
+ *
+ * The library runs the n-1 merge iterations of the Lance-Williams algorithm
+ * (Section 4, steps 1-4) over an n x n fp32 distance matrix held in device
+ * memory: each iteration takes the closest pair of live clusters and updates
+ * the merged cluster's row and column with the Table 1 coefficients.  All
+ * iterations of one instance run inside one persistent kernel launch.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a hac_status: HAC_OK (0) or a negative error.
+ *     No exception, abort() or exit() crosses this interface; the text of
+ *     the last error of a context is available from hac_last_error().
+ *   - Distance matrices are fp32, row-major, leading dimension n.  Only the
+ *     strict upper triangle (a < b) is read as input (Section 5.2: a distance
+ *     matrix needs only its upper half); diagonal and lower triangle are
+ *     ignored on input and overwritten.  Values must be finite with
+ *     |x| <= 2^100; -0 is treated as +0.  Otherwise HAC_EINPUT.
+ *   - A merge record is (i, j, height, size): slots 0 <= i < j < n; the
+ *     merged cluster keeps slot i and slot j is retired (Section 5.3, step 6),
+ *     so slot i is always the smallest original member of its cluster.
+ *     height is the distance of the pair at the merge, size the member count
+ *     of the merged cluster.  Ties between equal distances go to the
+ *     lexicographically smallest (i, j).
+ *   - Arithmetic: fp32 storage; single/complete are min/max (exact);
+ *     average and Ward evaluate the Table 1 formula in fp32 with
+ *     coefficients computed as fp64 quotients rounded once to fp32 and the
+ *     fixed order ((a_i*D_ki) + (a_j*D_kj)) [+ (beta*D_ij)], no fused
+ *     multiply-add; a zero result is stored as +0.
+ *   - n is limited to 1 <= n <= HAC_MAX_N.
+ *   - Thread safety: one context per host thread.  Calls on one context are
+ *     serialised by the caller.
+ */
+#ifndef HAC_H
+#define HAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HAC_MAX_N 65536
+
+typedef struct hac_ctx hac_ctx;
+
+typedef enum {
+    HAC_SINGLE = 0,   /* Table 1 row "Single Linkage":   min(D_ki, D_kj) */
+    HAC_COMPLETE = 1, /* Table 1 row "Complete Linkage": max(D_ki, D_kj) */
+    HAC_AVERAGE = 2,  /* Table 1 row "Group Average" */
+    HAC_WARD = 3      /* Table 1 row "Ward" */
+} hac_linkage;
+
+typedef struct {
+    int32_t i;      /* surviving slot */
+    int32_t j;      /* retired slot, i < j */
+    float height;   /* D_ij when merged */
+    int32_t size;   /* members of the merged cluster */
+} hac_merge;        /* 16 bytes */
+
+typedef enum {
+    HAC_OK = 0,
+    HAC_EINVAL = -1,    /* bad argument: n out of range, NULL pointer, bad linkage or flag */
+    HAC_EINPUT = -2,    /* non-finite or |x| > 2^100 value in a strict upper triangle */
+    HAC_ENOMEM = -3,    /* device memory for the workspace could not be allocated */
+    HAC_EDEVICE = -4,   /* a HIP call failed; see hac_last_error() */
+    HAC_ENODEV = -5,    /* no usable gfx950 device */
+    HAC_EBUSY = -6,     /* reserved */
+    HAC_ETIMEDOUT = -7, /* the persistent kernel's watchdog fired */
+    HAC_EINTERNAL = -8  /* an invariant of the algorithm was broken on the device */
+} hac_status;
+
+/* Flags for hac_run / hac_batch. */
+#define HAC_PRESERVE_INPUT (1u << 0) /* work on a library-owned copy; dist is left unchanged */
+#define HAC_OUT_DEVICE     (1u << 1) /* out is device memory; the call returns once the work is
+                                        enqueued on the stream, and hac_sync() reports its status */
+
+/*
+ * hac_create -- open a context on HIP device `device` (ordinal).
+ *   out: receives the context (owned by the caller, released by hac_destroy).
+ *   Errors: HAC_EINVAL (out NULL), HAC_ENODEV (no such device, or not
+ *   gfx950), HAC_EDEVICE.
+ */
+int hac_create(int device, hac_ctx **out);
+
+/* hac_destroy -- release the context and its device workspace.  NULL is a no-op. */
+int hac_destroy(hac_ctx *ctx);
+
+/*
+ * hac_run -- cluster one instance (Section 4, steps 1-4, iterated n-1 times).
+ *   dist:    device pointer, n*n fp32, row-major (caller-owned).  Used as the
+ *            working matrix and overwritten unless HAC_PRESERVE_INPUT.
+ *   n:       number of items, 1..HAC_MAX_N.  n == 1 yields no merges.
+ *   linkage: a hac_linkage value.
+ *   out:     n-1 records in merge order; host memory, or device memory with
+ *            HAC_OUT_DEVICE (caller-owned either way).
+ *   flags:   HAC_PRESERVE_INPUT | HAC_OUT_DEVICE.
+ *   stream:  hipStream_t to enqueue on; NULL = HIP's default (null) stream.
+ *   Without HAC_OUT_DEVICE the call blocks until out is filled and returns
+ *   the run's status; on HAC_EINPUT out is left untouched.
+ */
+int hac_run(hac_ctx *ctx, float *dist, int32_t n, int32_t linkage,
+            hac_merge *out, uint32_t flags, void *stream);
+
+/*
+ * hac_batch -- cluster `count` independent instances in one persistent launch.
+ *   packed:      device pointer; instance k's n_k x n_k matrix starts at
+ *                element offsets[k] (instances must not overlap).
+ *   offsets:     host int64[count], element offsets into packed.
+ *   ns:          host int32[count], sizes (each 1..HAC_MAX_BATCH_N).
+ *   linkages:    host int32[count].
+ *   out:         merge records; instance k's n_k-1 records start at record
+ *                out_offsets[k] (host int64[count]).  Host memory, or device
+ *                memory with HAC_OUT_DEVICE.
+ *   Each instance's records are byte-identical to hac_run on that instance.
+ */
+#define HAC_MAX_BATCH_N 8192
+int hac_batch(hac_ctx *ctx, float *packed, const int64_t *offsets, const int32_t *ns,
+              const int32_t *linkages, int32_t count, hac_merge *out,
+              const int64_t *out_offsets, uint32_t flags, void *stream);
+
+/* hac_sync -- wait for the context's last HAC_OUT_DEVICE call and return its status. */
+int hac_sync(hac_ctx *ctx);
+
+/* hac_last_error -- text of the context's last error ("" if none).  Valid until the next call. */
+const char *hac_last_error(const hac_ctx *ctx);
+
+/*
+ * Tuning options (hac_set_option).  Results never depend on them; they only
+ * change how work is spread over the GPU.
+ *   HAC_OPT_WORKGROUPS   workgroups cooperating on one hac_run instance
+ *                        (0 = automatic; clamped to what can be co-resident)
+ *   HAC_OPT_SINGLE_WG_N  hac_run uses one workgroup when n <= this (0 = automatic)
+ *   HAC_OPT_TIMEOUT_MS   watchdog for one wait inside the persistent kernel
+ *                        (0 = default 10000 ms); expiry returns HAC_ETIMEDOUT
+ */
+typedef enum {
+    HAC_OPT_WORKGROUPS = 1,
+    HAC_OPT_SINGLE_WG_N = 2,
+    HAC_OPT_TIMEOUT_MS = 3
+} hac_option;
+int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
+
+/*
+ * hac_stats -- figures of the context's last completed hac_run / hac_batch.
+ *   kernel_ms:         device time of the merge kernel (HIP events on the run's stream)
+ *   init_ms:           device time of the set-up kernels before it
+ *   rescans:           rows whose cached minimum was recomputed
+ *   rescan_elems:      matrix entries read by those recomputations
+ *   update_elems:      (k) entries updated by the Lance-Williams step, summed over merges
+ *   workgroups:        workgroups the merge kernel ran with
+ */
+typedef struct {
+    double kernel_ms;
+    double init_ms;
+    int64_t rescans;
+    int64_t rescan_elems;
+    int64_t update_elems;
+    int32_t workgroups;
+    int32_t reserved;
+} hac_stats;
+int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HAC_H */

@@ -42,7 +42,8 @@
  * Input: the strict upper triangle of the row-major n x n matrix is
  * authoritative (Section 5.2: only the upper half is needed); diagonal and
  * lower triangle are ignored.  Values must be finite with |x| <= 2^100;
- * -0 is read as +0.
+ * -0 is read as +0.  The working copy keeps only that upper half too: the
+ * distance between slots a != b lives at row min(a,b), column max(a,b).
  */
 #include <math.h>
 #include <stdint.h>
@@ -56,6 +57,9 @@ enum { OR_SINGLE = 0, OR_COMPLETE = 1, OR_AVERAGE = 2, OR_WARD = 3 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EINPUT = -2, OR_ENOMEM = -3, OR_EINTERNAL = -4 };
 
 #define OR_MAX_ABS 1.2676506002282294e30 /* 2^100 */
+
+/* Index of the stored distance between slots a != b (upper triangle). */
+#define UPPER(a, b) ((a) < (b) ? (a) * n + (b) : (b) * n + (a))
 
 /* ---- fp32 Lance-Williams update (Section 4 step 3, Table 1) ------------ */
 static float lw_f32(int link, float dki, float dkj, float dij,
@@ -142,14 +146,12 @@ int lw_oracle_f32(const float *dist, int64_t n, int link, int64_t max_merges,
     int64_t *sz = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     unsigned char *alive = (unsigned char *)malloc((size_t)n);
     if (!w || !sz || !alive) { free(w); free(sz); free(alive); return OR_ENOMEM; }
-    /* working copy: upper triangle authoritative, mirrored into the lower */
+    /* working copy of the upper triangle (the lower one is never used) */
     for (int64_t a = 0; a < n; a++) {
-        w[a * n + a] = 0.0f;
         for (int64_t b = a + 1; b < n; b++) {
             float x = dist[a * n + b];
             if (x == 0.0f) x = 0.0f; /* -0 -> +0 */
             w[a * n + b] = x;
-            w[b * n + a] = x;
         }
         sz[a] = 1;
         alive[a] = 1;
@@ -184,9 +186,8 @@ int lw_oracle_f32(const float *dist, int64_t n, int link, int64_t max_merges,
         /* step 3: Lance-Williams update of row/column i */
         for (int64_t k = 0; k < n; k++) {
             if (!alive[k] || k == i || k == j) continue;
-            float v = lw_f32(link, w[k * n + i], w[k * n + j], h, sz[i], sz[j], sz[k]);
-            w[i * n + k] = v;
-            w[k * n + i] = v;
+            float v = lw_f32(link, w[UPPER(k, i)], w[UPPER(k, j)], h, sz[i], sz[j], sz[k]);
+            w[UPPER(k, i)] = v;
         }
         /* step 2 bookkeeping: j retired, i holds the merged cluster */
         alive[j] = 0;
@@ -217,12 +218,10 @@ int lw_oracle_f64(const double *dist, int64_t n, int link, int64_t max_merges,
     unsigned char *alive = (unsigned char *)malloc((size_t)n);
     if (!w || !sz || !alive) { free(w); free(sz); free(alive); return OR_ENOMEM; }
     for (int64_t a = 0; a < n; a++) {
-        w[a * n + a] = 0.0;
         for (int64_t b = a + 1; b < n; b++) {
             double x = dist[a * n + b];
             if (x == 0.0) x = 0.0;
             w[a * n + b] = x;
-            w[b * n + a] = x;
         }
         sz[a] = 1;
         alive[a] = 1;
@@ -255,9 +254,8 @@ int lw_oracle_f64(const double *dist, int64_t n, int link, int64_t max_merges,
         double h = best;
         for (int64_t k = 0; k < n; k++) {
             if (!alive[k] || k == i || k == j) continue;
-            double v = lw_f64(link, w[k * n + i], w[k * n + j], h, sz[i], sz[j], sz[k]);
-            w[i * n + k] = v;
-            w[k * n + i] = v;
+            double v = lw_f64(link, w[UPPER(k, i)], w[UPPER(k, j)], h, sz[i], sz[j], sz[k]);
+            w[UPPER(k, i)] = v;
         }
         alive[j] = 0;
         sz[i] += sz[j];
@@ -288,12 +286,10 @@ int lw_replay_f64(const float *dist, int64_t n, int link, int64_t count,
     unsigned char *alive = (unsigned char *)malloc((size_t)n);
     if (!w || !sz || !alive) { free(w); free(sz); free(alive); return OR_ENOMEM; }
     for (int64_t a = 0; a < n; a++) {
-        w[a * n + a] = 0;
         for (int64_t b = a + 1; b < n; b++) {
             double x = (double)dist[a * n + b];
             if (x == 0) x = 0;
             w[a * n + b] = x;
-            w[b * n + a] = x;
         }
         sz[a] = 1;
         alive[a] = 1;
@@ -318,9 +314,8 @@ int lw_replay_f64(const float *dist, int64_t n, int link, int64_t count,
         double h = w[i * n + j];
         for (int64_t k = 0; k < n; k++) {
             if (!alive[k] || k == i || k == j) continue;
-            double v = lw_f64(link, w[k * n + i], w[k * n + j], h, sz[i], sz[j], sz[k]);
-            w[i * n + k] = v;
-            w[k * n + i] = v;
+            double v = lw_f64(link, w[UPPER(k, i)], w[UPPER(k, j)], h, sz[i], sz[j], sz[k]);
+            w[UPPER(k, i)] = v;
         }
         alive[j] = 0;
         sz[i] += sz[j];

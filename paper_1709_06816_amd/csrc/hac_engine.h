@@ -1,0 +1,72 @@
+// Internal interface between the C-ABI layer (hac_api.cpp) and the device
+// engine (hac_engine.hip).  Not installed; the public interface is hac.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hac.h"
+
+namespace hac {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kChunk = 64;           // rows owned in chunks of 64 (one wave's lanes)
+constexpr int kTile = 64;            // mirror tile edge
+constexpr int kSlotStride = 512;     // u64 words between exchange slots (4 KiB)
+
+// Device status words of one launch.
+enum : uint32_t {
+    kErrInput = 1u,     // non-finite or out-of-range input
+    kErrTimeout = 2u,   // a wait exceeded the watchdog
+    kErrInternal = 4u,  // no live pair found although >= 2 clusters remain
+};
+
+struct Control {
+    uint32_t error;            // OR of kErr* over the launch
+    uint32_t abort;            // set by a workgroup that gives up: every wait exits
+    uint32_t next;             // batch work queue head
+    uint32_t pad0;
+    unsigned long long rescans;
+    unsigned long long rescan_elems;
+    unsigned long long update_elems;
+    unsigned long long pad1[3];
+};
+
+// One clustering instance as the engine sees it.
+struct Instance {
+    float *D;            // working matrix, n x n, leading dimension n
+    hac_merge *out;      // n-1 records (device)
+    int32_t *gsize;      // cluster sizes, n entries (used when g > 1)
+    uint64_t *slots;     // exchange slots: 2 * g * kSlotStride words (g > 1)
+    uint32_t *status;    // per-instance kErr* word
+    int32_t n;
+    int32_t link;
+};
+
+// Bytes of dynamic LDS one workgroup needs to own `own` rows of an n-item
+// instance.
+size_t lds_bytes(int n, int own);
+// Rows a workgroup owns when g workgroups share n items.
+int own_rows(int n, int g);
+
+// Fill `words` u32 with zero on `stream` (a kernel, not a memset node).
+hipError_t launch_zero(void *p, size_t words, hipStream_t stream);
+
+// One instance on g workgroups (g > 1 uses a cooperative launch so that all
+// are co-resident).
+hipError_t launch_run(const Instance &inst, int g, Control *ctl, uint64_t timeout_ticks,
+                      hipStream_t stream);
+
+// `count` instances, one workgroup each, taken in the order of `order`
+// (device int32[count]) from a queue; grid workgroups.
+hipError_t launch_batch(const Instance *insts, const int32_t *order, int count, int grid,
+                        size_t lds, Control *ctl, uint64_t timeout_ticks, hipStream_t stream);
+
+// Kernel attribute set-up (dynamic LDS limits); call once per device.
+hipError_t engine_setup(size_t max_lds);
+
+// Workgroups of the run (batch = false) or batch kernel that fit on one CU
+// with `lds` bytes of dynamic LDS.
+int engine_occupancy(size_t lds, bool batch);
+
+}  // namespace hac

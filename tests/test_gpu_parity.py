@@ -1,0 +1,278 @@
+"""GPU parity: the HIP library, called through its C-ABI, against the CPU
+oracle on the same seeded inputs.  Merge lists must be byte-identical
+(indices, fp32 heights and sizes): single/complete are exact, average/Ward
+follow the same fixed fp32 recipe on both sides.
+
+At the full n=32768 RMSD-like size the oracle cannot run to the end in a
+test, so there the GPU list is checked on its first merges against the
+oracle's, and as a whole through an fp64 replay (heights within 1e-5
+relative, sampled optimality) and structural invariants.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+LINKS = ["single", "complete", "average", "ward"]
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_1709_06816_amd as hac
+    c = hac.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_run(ctx, torch, d, link, **opts):
+    import paper_1709_06816_amd as hac
+    for k, v in opts.items():
+        ctx.set_option({"workgroups": hac.OPT_WORKGROUPS, "single_wg_n": hac.OPT_SINGLE_WG_N}[k], v)
+    try:
+        t = torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda()
+        res = ctx.run(t, link)
+        torch.cuda.synchronize()
+        return res
+    finally:
+        for k in opts:
+            ctx.set_option({"workgroups": hac.OPT_WORKGROUPS, "single_wg_n": hac.OPT_SINGLE_WG_N}[k], 0)
+
+
+def _same(a, b):
+    return a.dtype.itemsize == b.dtype.itemsize == 16 and a.tobytes() == b.tobytes()
+
+
+def _diff(a, b):
+    for s in range(min(len(a), len(b))):
+        if a[s].tobytes() != b[s].tobytes():
+            return "first difference at merge %d: gpu %r oracle %r" % (s, a[s], b[s])
+    return "lengths %d vs %d" % (len(a), len(b))
+
+
+# ---------------------------------------------------------------------------
+# Small and edge sizes, single workgroup and multi-workgroup paths
+# ---------------------------------------------------------------------------
+
+EDGE_NS = [2, 3, 5, 63, 64, 65, 127, 129, 300, 1000]
+
+
+@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("n", EDGE_NS)
+def test_edge_sizes_single_wg(ctx, torch, n, link):
+    d = synth.mixture_8192(seed=1000 + n, n=n)
+    _say("edge single-wg n=%d %s" % (n, link))
+    got = _gpu_run(ctx, torch, d, link)
+    exp = oracle.run_f32(d, link)
+    assert _same(got, exp), _diff(got, exp)
+
+
+@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("n,wgs", [(65, 2), (129, 3), (300, 5), (1000, 7), (1000, 16), (2500, 40)])
+def test_edge_sizes_multi_wg(ctx, torch, n, wgs, link):
+    d = synth.mixture_8192(seed=2000 + n, n=n)
+    _say("edge multi-wg n=%d wgs=%d %s" % (n, wgs, link))
+    got = _gpu_run(ctx, torch, d, link, single_wg_n=1, workgroups=wgs)
+    exp = oracle.run_f32(d, link)
+    assert _same(got, exp), _diff(got, exp)
+
+
+@pytest.mark.parametrize("link", LINKS)
+def test_tie_heavy(ctx, torch, link):
+    """Quantised and constant matrices: ties everywhere, resolved to the
+    smallest (i, j) on both sides."""
+    for n, d in ((400, synth.quantized_matrix(400, 5, levels=3)),
+                 (257, np.full((257, 257), 1.5, np.float32)),
+                 (700, synth.rmsd_like(seed=77, n=700))):
+        for opts in ({}, {"single_wg_n": 1, "workgroups": 9}):
+            _say("ties n=%d %s %r" % (n, link, opts))
+            got = _gpu_run(ctx, torch, d, link, **opts)
+            exp = oracle.run_f32(d, link)
+            assert _same(got, exp), _diff(got, exp)
+
+
+def test_hand_worked_cases(ctx, torch):
+    import json
+    from conftest import matrix_from_upper
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "hand_worked.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        d = matrix_from_upper(case["n"], case["upper"], fill_lower=0.0)
+        for link in LINKS:
+            got = _gpu_run(ctx, torch, d, link)
+            exp = case["expected"][link]
+            assert [(int(g["i"]), int(g["j"]), float(g["h"]), int(g["size"])) for g in got] == \
+                [(e[0], e[1], float(np.float32(e[2])), e[3]) for e in exp], (case["name"], link)
+
+
+def test_mixture_512_complete(ctx, torch):
+    """n=512 complete linkage, 8 isotropic Gaussians in R^8."""
+    d = synth.mixture_512()
+    _say("mixture_512")
+    got = _gpu_run(ctx, torch, d, "complete")
+    exp = oracle.run_f32(d, "complete")
+    assert _same(got, exp), _diff(got, exp)
+
+
+def test_workgroup_sweep_identical(ctx, torch):
+    """The merge list does not depend on how many workgroups share the work."""
+    d = synth.rmsd_like(seed=91, n=3000)
+    ref = oracle.run_f32(d, "complete")
+    for wgs in (1, 2, 8, 32, 47, 0):
+        opts = {"single_wg_n": 1, "workgroups": wgs} if wgs != 1 else {"single_wg_n": 4096}
+        _say("sweep wgs=%d" % wgs)
+        got = _gpu_run(ctx, torch, d, "complete", **opts)
+        assert _same(got, ref), (wgs, _diff(got, ref))
+
+
+def test_input_conventions(ctx, torch):
+    """Lower triangle ignored, -0 read as +0, non-finite rejected."""
+    import paper_1709_06816_amd as hac
+    d = synth.quantized_matrix(200, 4)
+    d[3, 10] = -0.0
+    junk = d.copy()
+    il = np.tril_indices(200, 0)
+    junk[il] = np.nan
+    exp = oracle.run_f32(d, "average")
+    assert _same(_gpu_run(ctx, torch, junk, "average"), exp)
+    bad = d.copy()
+    bad[5, 150] = np.inf
+    with pytest.raises(hac.HacError) as e:
+        _gpu_run(ctx, torch, bad, "average")
+    assert e.value.code == hac.HAC_EINPUT
+    bad[5, 150] = 2.0 ** 101
+    with pytest.raises(hac.HacError) as e:
+        _gpu_run(ctx, torch, bad, "average", single_wg_n=1, workgroups=4)
+    assert e.value.code == hac.HAC_EINPUT
+    # the context still works after an input error
+    assert _same(_gpu_run(ctx, torch, d, "average"), exp)
+
+
+def test_preserve_and_determinism(ctx, torch):
+    d = synth.mixture_8192(seed=5, n=1500)
+    t = torch.from_numpy(d).cuda()
+    a = ctx.run(t, "ward", preserve=True)
+    assert torch.equal(t.cpu(), torch.from_numpy(d))
+    b = ctx.run(t, "ward", preserve=True)
+    assert _same(a, b)
+    assert _same(a, oracle.run_f32(d, "ward"))
+
+
+def test_n1_and_errors(ctx, torch):
+    import paper_1709_06816_amd as hac
+    t = torch.zeros((1, 1), device="cuda")
+    assert len(ctx.run(t, "single")) == 0
+    with pytest.raises(hac.HacError) as e:
+        ctx.run(torch.zeros((4, 4), device="cuda"), 9)
+    assert e.value.code == hac.HAC_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# Batched launch
+# ---------------------------------------------------------------------------
+
+def test_batch_matches_oracle_and_run(ctx, torch):
+    spec = synth.batch_spec(count=48, n_lo=64, n_hi=900, seed=4242)
+    mats = [synth.batch_instance(n, s) for n, s in zip(spec.ns, spec.seeds)]
+    offs, total = synth.pack_offsets(spec.ns)
+    packed = np.zeros(total, np.float32)
+    for k, m in enumerate(mats):
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+    _say("batch 48")
+    t = torch.from_numpy(packed).cuda()
+    res = ctx.batch(t, offs, spec.ns, spec.linkages, preserve=True)
+    moff, _ = synth.merge_offsets(spec.ns)
+    for k, m in enumerate(mats):
+        n = int(spec.ns[k])
+        got = res[moff[k]:moff[k] + n - 1]
+        exp = oracle.run_f32(m, int(spec.linkages[k]))
+        assert _same(got, exp), (k, n, _diff(got, exp))
+        if k % 8 == 0:
+            single = _gpu_run(ctx, torch, m, int(spec.linkages[k]))
+            assert _same(got, single)
+
+
+def test_batch_ragged_edges(ctx, torch):
+    ns = np.array([1, 2, 3, 64, 65, 5, 130, 1], np.int64)
+    links = np.array([0, 1, 2, 3, 0, 1, 2, 3], np.int32)
+    mats = [synth.uniform_matrix(int(n), 50 + k) for k, n in enumerate(ns)]
+    offs, total = synth.pack_offsets(ns)
+    packed = np.zeros(total, np.float32)
+    for k, m in enumerate(mats):
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+    res = ctx.batch(torch.from_numpy(packed).cuda(), offs, ns, links)
+    moff, _ = synth.merge_offsets(ns)
+    for k, m in enumerate(mats):
+        n = int(ns[k])
+        exp = oracle.run_f32(m, int(links[k]))
+        assert _same(res[moff[k]:moff[k] + n - 1], exp), k
+
+
+# ---------------------------------------------------------------------------
+# Larger sizes
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("link", LINKS)
+def test_mixture_8192(ctx, torch, link):
+    """n=8192, 32 Gaussians in R^16: full list byte-identical to the oracle."""
+    d = synth.mixture_8192()
+    _say("mixture_8192 %s" % link)
+    got = _gpu_run(ctx, torch, d, link)
+    exp = oracle.run_f32(d, link)
+    assert _same(got, exp), _diff(got, exp)
+    h64, _ = oracle.replay_f64(d, link, got)
+    assert np.all(np.abs(got["h"].astype(np.float64) - h64) <= 1e-5 * np.abs(h64) + 1e-30)
+
+
+def _check_structure(m, n):
+    """Merge-list invariants: n-1 merges, i < j, j retired exactly once and
+    never used again, sizes add up, survivor is the smallest member."""
+    assert len(m) == n - 1
+    alive = np.ones(n, bool)
+    size = np.ones(n, np.int64)
+    for r in m:
+        i, j = int(r["i"]), int(r["j"])
+        assert 0 <= i < j < n and alive[i] and alive[j]
+        size[i] += size[j]
+        assert int(r["size"]) == size[i]
+        alive[j] = False
+    assert alive.sum() == 1 and alive[0]
+
+
+def test_rmsd_like_32768_complete(ctx, torch):
+    """n=32768 RMSD-like complete linkage: first 40 merges byte-identical to
+    the oracle's, complete-linkage heights non-decreasing, structure valid,
+    fp64 replay heights within 1e-5 and sampled optimality."""
+    n = 32768
+    d = synth.rmsd_like()
+    _say("rmsd_like 32768 gpu")
+    got = _gpu_run(ctx, torch, d, "complete")
+    _check_structure(got, n)
+    assert np.all(np.diff(got["h"]) >= 0)
+    _say("rmsd_like 32768 oracle prefix")
+    exp = oracle.run_f32(d, "complete", max_merges=40)
+    assert _same(got[:40], exp), _diff(got[:40], exp)
+    _say("rmsd_like 32768 replay")
+    h64, min64 = oracle.replay_f64(d, "complete", got, opt_stride=4096)
+    assert np.all(np.abs(got["h"].astype(np.float64) - h64) <= 1e-5 * np.abs(h64))
+    sel = ~np.isnan(min64)
+    assert np.all(h64[sel] <= min64[sel])

@@ -29,7 +29,7 @@ MUTANTS = {
     "complete_uses_min": ("v = fmaxf(dki, dkj);", "v = fminf(dki, dkj);"),
     "tie_prefers_later_row": ("if (a != ba) return a < ba;", "if (a != ba) return a > ba;"),
     "tie_prefers_later_col": ("return b < bb;", "return b > bb;"),
-    "update_reads_i_twice": ("w[k * n + i], w[k * n + j], h,", "w[k * n + i], w[k * n + i], h,"),
+    "update_reads_i_twice": ("w[UPPER(k, i)], w[UPPER(k, j)], h,", "w[UPPER(k, i)], w[UPPER(k, i)], h,"),
     "size_not_accumulated": ("sz[i] += sz[j];", "sz[i] += 1;"),
     "scan_skips_neighbour": ("for (int64_t b = a + 1; b < n; b++)\n                    if (alive[b]",
                              "for (int64_t b = a + 2; b < n; b++)\n                    if (alive[b]"),
