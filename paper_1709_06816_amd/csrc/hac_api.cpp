@@ -218,10 +218,13 @@ int hac_create(int device, hac_ctx **out) {
             return HAC_EDEVICE;
         }
     }
-    if (hac::engine_setup(c->lds_max) != hipSuccess) {
+    size_t usable = 0;
+    if (hac::engine_setup(c->lds_max, &usable) != hipSuccess) {
+        (void)hipGetLastError();
         hac_destroy(c);
         return HAC_EDEVICE;
     }
+    c->lds_max = usable;
     *out = c;
     return HAC_OK;
 }

@@ -63,7 +63,9 @@ hipError_t launch_batch(const Instance *insts, const int32_t *order, int count, 
                         size_t lds, Control *ctl, uint64_t timeout_ticks, hipStream_t stream);
 
 // Kernel attribute set-up (dynamic LDS limits); call once per device.
-hipError_t engine_setup(size_t max_lds);
+// `max_lds` is the device's LDS per workgroup; *usable receives the dynamic
+// LDS a launch may request.
+hipError_t engine_setup(size_t max_lds, size_t *usable);
 
 // Workgroups of the run (batch = false) or batch kernel that fit on one CU
 // with `lds` bytes of dynamic LDS.

@@ -330,6 +330,10 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
     }
 
     int i_prev = -1;
+    // Size of the cluster formed by the previous merge.  Every workgroup
+    // carries it in a register; its owner writes it to gsize one merge later,
+    // when no workgroup can still be reading the old value.
+    int last_size = 0;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
         if (g > 1) {
@@ -376,8 +380,10 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
             ni = (int)(L.cache[i] & 0xFFFFull) + 1;
             nj = (int)(L.cache[j] & 0xFFFFull) + 1;
         } else {
-            ni = __hip_atomic_load(I.gsize + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            nj = __hip_atomic_load(I.gsize + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ni = i == i_prev ? last_size
+                             : __hip_atomic_load(I.gsize + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            nj = j == i_prev ? last_size
+                             : __hip_atomic_load(I.gsize + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // ---- output the level (Section 4 step 4) -------------------------
         if (w == 0 && tid == 0) {
@@ -398,8 +404,10 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
             if (owner_of_row(i, g) == w) {
                 const int li = local_of_row(i, g);
                 L.cache[li] = (L.cache[li] & ~0xFFFFull) | (uint64_t)(ni + nj - 1);
-                if (g > 1) I.gsize[i] = ni + nj;
             }
+            // Other workgroups read gsize[i] for this merge; the new size of i
+            // is published during the next one (they use last_size meanwhile).
+            if (g > 1 && i_prev >= 0 && owner_of_row(i_prev, g) == w) I.gsize[i_prev] = last_size;
         }
         __syncthreads();
 
@@ -480,6 +488,7 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
             p1 = umin64(p1, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
         }
         i_prev = i;
+        last_size = ni + nj;
     }
 }
 
@@ -534,12 +543,22 @@ size_t lds_bytes(int n, int own) {
     return (size_t)own * 8 + (size_t)own * 2 + mask_words * 4 + (size_t)kTile * (kTile + 1) * 4;
 }
 
-hipError_t engine_setup(size_t max_lds) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+hipError_t engine_setup(size_t max_lds, size_t *usable) {
+    // Dynamic LDS may use what the static LDS of the kernels leaves free.
+    size_t static_max = 0;
+    for (const void *fn : {reinterpret_cast<const void *>(&k_run), reinterpret_cast<const void *>(&k_batch)}) {
+        hipFuncAttributes a;
+        hipError_t e = hipFuncGetAttributes(&a, fn);
+        if (e != hipSuccess) return e;
+        static_max = a.sharedSizeBytes > static_max ? a.sharedSizeBytes : static_max;
+    }
+    const size_t dyn = max_lds > static_max ? max_lds - static_max : 0;
+    for (const void *fn : {reinterpret_cast<const void *>(&k_run), reinterpret_cast<const void *>(&k_batch)}) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+        if (e != hipSuccess) return e;
+    }
+    *usable = dyn;
+    return hipSuccess;
 }
 
 int engine_occupancy(size_t lds, bool batch) {
