@@ -134,11 +134,15 @@ const char *hac_last_error(const hac_ctx *ctx);
  *   HAC_OPT_SINGLE_WG_N  hac_run uses one workgroup when n <= this (0 = automatic)
  *   HAC_OPT_TIMEOUT_MS   watchdog for one wait inside the persistent kernel
  *                        (0 = default 10000 ms); expiry returns HAC_ETIMEDOUT
+ *   HAC_OPT_EXCHANGE     how the workgroups of one instance agree on each merge:
+ *                        0 = every workgroup reads every partial result,
+ *                        1 = workgroup 0 reads them and broadcasts the minimum
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
     HAC_OPT_SINGLE_WG_N = 2,
-    HAC_OPT_TIMEOUT_MS = 3
+    HAC_OPT_TIMEOUT_MS = 3,
+    HAC_OPT_EXCHANGE = 4
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 
@@ -150,6 +154,12 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *   rescan_elems:      matrix entries read by those recomputations
  *   update_elems:      (k) entries updated by the Lance-Williams step, summed over merges
  *   workgroups:        workgroups the merge kernel ran with
+ *   phase_avg_ms[5]:   time per workgroup (device wall clock), averaged over the
+ *                      workgroups, spent in: [0] set-up (mirror, checks, first
+ *                      row minima), [1] waiting for / combining the group's
+ *                      partial minima, [2] the Lance-Williams update, [3] row
+ *                      rescans, [4] local candidate reduction
+ *   phase_max_ms[5]:   the same, largest workgroup
  */
 typedef struct {
     double kernel_ms;
@@ -159,6 +169,8 @@ typedef struct {
     int64_t update_elems;
     int32_t workgroups;
     int32_t reserved;
+    double phase_avg_ms[5];
+    double phase_max_ms[5];
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

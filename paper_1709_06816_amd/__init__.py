@@ -33,7 +33,7 @@ HAC_OK, HAC_EINVAL, HAC_EINPUT, HAC_ENOMEM, HAC_EDEVICE, HAC_ENODEV, HAC_EBUSY, 
     HAC_ETIMEDOUT, HAC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PRESERVE_INPUT = 1
 OUT_DEVICE = 2
-OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS = 1, 2, 3
+OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE = 1, 2, 3, 4
 MAX_N = 65536
 MAX_BATCH_N = 8192
 
@@ -59,7 +59,11 @@ class _Stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("init_ms", ctypes.c_double),
                 ("rescans", ctypes.c_int64), ("rescan_elems", ctypes.c_int64),
                 ("update_elems", ctypes.c_int64), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("phase_avg_ms", ctypes.c_double * 5),
+                ("phase_max_ms", ctypes.c_double * 5)]
+
+
+PHASES = ("setup", "exchange", "update", "rescan", "candidates")
 
 
 _lock = threading.Lock()
@@ -162,7 +166,11 @@ class Context:
     def stats(self) -> dict:
         s = _Stats()
         self._check(self._lib.hac_get_stats(self._h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in _Stats._fields_ if f != "reserved"}
+        out = {f: getattr(s, f) for f, _ in _Stats._fields_
+               if f not in ("reserved", "phase_avg_ms", "phase_max_ms")}
+        out["phase_avg_ms"] = dict(zip(PHASES, list(s.phase_avg_ms)))
+        out["phase_max_ms"] = dict(zip(PHASES, list(s.phase_max_ms)))
+        return out
 
     def run(self, dist, linkage, preserve: bool = False, out=None, stream=None) -> np.ndarray:
         """Cluster one n x n fp32 device matrix.  Returns MERGE_DTYPE[n-1].

@@ -43,7 +43,7 @@ struct hac_ctx {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 
     hac_stats stats{};
-    int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0;
+    int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0, opt_exchange = 0;
 
     // State of the last enqueued call, for hac_sync / stats.
     bool pending = false;
@@ -153,6 +153,11 @@ int check_status(hac_ctx *c) {
     c->stats.rescan_elems = (int64_t)ctl->rescan_elems;
     c->stats.update_elems = (int64_t)ctl->update_elems;
     c->stats.workgroups = c->pending_wgs;
+    const double khz = c->wallclock_khz > 0 ? c->wallclock_khz : 100000.0;
+    for (int p = 0; p < 5; ++p) {
+        c->stats.phase_avg_ms[p] = (double)ctl->prof_sum[p] / khz / std::max(1, c->pending_wgs);
+        c->stats.phase_max_ms[p] = (double)ctl->prof_max[p] / khz;
+    }
     for (int k = 0; k < c->pending_count; ++k) {
         if (st[k] & hac::kErrInput)
             return fail(c, HAC_EINPUT, "instance %d: non-finite or |x| > 2^100 value in the strict upper triangle", k);
@@ -254,6 +259,10 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
     case HAC_OPT_WORKGROUPS: c->opt_wgs = value; return HAC_OK;
     case HAC_OPT_SINGLE_WG_N: c->opt_single_n = value; return HAC_OK;
     case HAC_OPT_TIMEOUT_MS: c->opt_timeout_ms = value; return HAC_OK;
+    case HAC_OPT_EXCHANGE:
+        if (value > 1) return fail(c, HAC_EINVAL, "exchange mode %lld", (long long)value);
+        c->opt_exchange = value;
+        return HAC_OK;
     default: return fail(c, HAC_EINVAL, "unknown option %d", option);
     }
 }
@@ -316,7 +325,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     const size_t st_off = ctl_bytes, st_bytes = kAlign;
     const size_t gs_off = st_off + st_bytes, gs_bytes = align_up((size_t)n * 4, kAlign);
     const size_t sl_off = gs_off + gs_bytes;
-    const size_t sl_bytes = g > 1 ? (size_t)2 * g * hac::kSlotStride * 8 : 0;
+    const size_t sl_bytes = g > 1 ? (size_t)2 * (g + 1) * hac::kSlotStride * 8 : 0;
     rc = ensure_dev(c, &c->ws, &c->ws_cap, sl_off + sl_bytes, "workspace");
     if (rc) return rc;
     rc = ensure_pinned(c, ctl_bytes + kAlign);
@@ -348,6 +357,8 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     inst.status = reinterpret_cast<uint32_t *>(ws + st_off);
     inst.n = n;
     inst.link = linkage;
+    inst.exchange = (int32_t)c->opt_exchange;
+    inst.pad = 0;
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
@@ -433,6 +444,8 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         I.status = reinterpret_cast<uint32_t *>(ws + st_off) + k;
         I.n = ns[k];
         I.link = linkages[k];
+        I.exchange = 0;
+        I.pad = 0;
     }
     std::vector<int32_t> ord(count);
     std::iota(ord.begin(), ord.end(), 0);

@@ -21,6 +21,15 @@ enum : uint32_t {
     kErrInternal = 4u,  // no live pair found although >= 2 clusters remain
 };
 
+// Phases timed by each workgroup (device wall clock).
+enum : int { kPhSetup = 0, kPhWait = 1, kPhUpdate = 2, kPhRescan = 3, kPhCand = 4, kPhases = 5 };
+
+// Exchange between the workgroups of a group (tuning only; results identical).
+enum : int {
+    kExchAllToAll = 0,  // every workgroup polls every slot
+    kExchReducer = 1,   // workgroup 0 polls every slot and broadcasts the minimum
+};
+
 struct Control {
     uint32_t error;            // OR of kErr* over the launch
     uint32_t abort;            // set by a workgroup that gives up: every wait exits
@@ -29,7 +38,8 @@ struct Control {
     unsigned long long rescans;
     unsigned long long rescan_elems;
     unsigned long long update_elems;
-    unsigned long long pad1[3];
+    unsigned long long prof_sum[8];   // per phase, summed over workgroups (wall-clock ticks)
+    unsigned long long prof_max[8];   // per phase, largest workgroup total
 };
 
 // One clustering instance as the engine sees it.
@@ -37,10 +47,12 @@ struct Instance {
     float *D;            // working matrix, n x n, leading dimension n
     hac_merge *out;      // n-1 records (device)
     int32_t *gsize;      // cluster sizes, n entries (used when g > 1)
-    uint64_t *slots;     // exchange slots: 2 * g * kSlotStride words (g > 1)
+    uint64_t *slots;     // exchange slots: 2 * (g + 1) * kSlotStride words (g > 1)
     uint32_t *status;    // per-instance kErr* word
     int32_t n;
     int32_t link;
+    int32_t exchange;    // kExch* (g > 1)
+    int32_t pad;
 };
 
 // Bytes of dynamic LDS one workgroup needs to own `own` rows of an n-item

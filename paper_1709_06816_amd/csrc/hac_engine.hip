@@ -119,6 +119,7 @@ struct Lds {
 __shared__ uint64_t s_red[2][kWaves];
 __shared__ uint32_t s_nresc;
 __shared__ int s_inst;
+__shared__ uint32_t s_fail;
 
 // Minimum of (a, b) over the workgroup, returned to every thread.
 __device__ void block_min2(uint64_t &a, uint64_t &b) {
@@ -153,24 +154,54 @@ __device__ unsigned long long block_sum(unsigned long long v) {
 }
 
 // Smallest (D[k][l], l) over live l > k; kEmpty if none.  Whole workgroup.
-// `elems` counts the live entries this thread compared.
+// `elems` counts the live entries this thread compared.  Rows are read with
+// 16-byte loads when n is a multiple of 4 (row starts are then aligned).
 __device__ uint64_t rescan_row(const float *__restrict__ D, int n, int k, const uint32_t *amask,
                                unsigned long long &elems) {
     const float *row = D + (size_t)k * n;
     uint64_t best = kEmpty;
-    for (int l0 = k + 1 + (int)threadIdx.x; l0 < n; l0 += kScanUnroll * kBlock) {
-        float x[kScanUnroll];
+    if ((n & 3) == 0) {
+        const float4 *r4 = reinterpret_cast<const float4 *>(row);
+        const int nq = n >> 2;
+        for (int q0 = ((k + 1) >> 2) + (int)threadIdx.x; q0 < nq; q0 += kScanUnroll * kBlock) {
+            float4 x[kScanUnroll];
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-            int l = l0 + u * kBlock;
-            x[u] = l < n ? row[l] : 0.0f;
+            for (int u = 0; u < kScanUnroll; ++u) {
+                const int q = q0 + u * kBlock;
+                x[u] = q < nq ? r4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                const int q = q0 + u * kBlock;
+                if (q >= nq) continue;
+                // live bits of l = 4q .. 4q+3, restricted to l > k
+                uint32_t m = (amask[q >> 3] >> ((q & 7) * 4)) & 0xFu;
+                const int below = k + 1 - 4 * q;  // entries l < k+1 inside this quad
+                if (below > 0) m &= (0xFu << below) & 0xFu;
+                if (!m) continue;
+                elems += __popc(m);
+                const float v[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if ((m >> c) & 1u)
+                        best = umin64(best, ((uint64_t)ord32(v[c]) << 32) | ((uint64_t)(4 * q + c) << 16));
+            }
         }
+    } else {
+        for (int l0 = k + 1 + (int)threadIdx.x; l0 < n; l0 += kScanUnroll * kBlock) {
+            float x[kScanUnroll];
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-            int l = l0 + u * kBlock;
-            if (l < n && is_live(amask, l)) {
-                best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
-                ++elems;
+            for (int u = 0; u < kScanUnroll; ++u) {
+                int l = l0 + u * kBlock;
+                x[u] = l < n ? row[l] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                int l = l0 + u * kBlock;
+                if (l < n && is_live(amask, l)) {
+                    best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
+                    ++elems;
+                }
             }
         }
     }
@@ -235,59 +266,98 @@ __device__ void setup_rows(const Instance &I, int g, int w, Lds &L) {
 
 struct Stats {
     unsigned long long rescans = 0, rescan_elems = 0, update_elems = 0;
+    unsigned long long prof[kPhases] = {0, 0, 0, 0, 0};  // thread 0 only
+    uint64_t mark = 0;
+    // Charge the time since the last mark to phase p (thread 0).
+    __device__ __forceinline__ void lap(int p) {
+        if (threadIdx.x == 0) {
+            const uint64_t now = wall_clock64();
+            prof[p] += now - mark;
+            mark = now;
+        }
+    }
 };
 
-// Poll every slot of the group for generation `epoch`, reduce, and return the
-// group-wide minima.  Returns false if the wait was abandoned.
-__device__ bool group_exchange(const Instance &I, int g, int w, uint32_t epoch, uint64_t &p1,
-                               uint64_t &p2, Control *ctl, uint64_t timeout) {
-    block_min2(p1, p2);
-    const uint64_t gen = epoch & 0xFFFFu;
-    uint64_t *base = I.slots + (size_t)(epoch & 1u) * g * kSlotStride;
-    if (threadIdx.x == 0) {
-        uint64_t *s = base + (size_t)w * kSlotStride;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(s + 0, (p1 & ~0xFFFFull) | gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(s + 1, ((p1 & 0xFFFFull) << 16) | gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(s + 2, (p2 & ~0xFFFFull) | gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    uint64_t m1 = kEmpty, m2 = kEmpty;
-    int failed = 0;
-    for (int t = threadIdx.x; t < g && !failed; t += kBlock) {
-        const uint64_t *s = base + (size_t)t * kSlotStride;
-        const uint64_t t0 = wall_clock64();
-        uint64_t a, b, c;
-        for (uint32_t it = 1;; ++it) {
-            a = __hip_atomic_load(s + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            b = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            c = __hip_atomic_load(s + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((a & 0xFFFFull) == gen && (b & 0xFFFFull) == gen && (c & 0xFFFFull) == gen) break;
-            if ((it & 63u) == 0) {
-                if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    failed = 1;
-                    break;
-                }
-                if (wall_clock64() - t0 > timeout) {
-                    atomicOr(&ctl->error, kErrTimeout);
-                    atomicOr(I.status, kErrTimeout);
-                    __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    failed = 1;
-                    break;
-                }
+// Slot format (three u64, each carrying the 16-bit generation in its low
+// bits so that a reader can tell a fresh word from an old one):
+//   w0 = (p1 with its low 16 bits cleared) | gen      p1 = ord:32 | row:16 | partner:16
+//   w1 = (partner of p1) << 16 | gen
+//   w2 = (p2 with its low 16 bits cleared) | gen      p2 = ord:32 | column:16 | 0
+__device__ __forceinline__ void put_slot(uint64_t *s, uint64_t p1, uint64_t p2, uint64_t gen) {
+    __hip_atomic_store(s + 0, (p1 & ~0xFFFFull) | gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(s + 1, ((p1 & 0xFFFFull) << 16) | gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(s + 2, (p2 & ~0xFFFFull) | gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until slot s holds generation gen.  Returns false if the launch was
+// aborted or the watchdog expired (then the abort flag is raised for all).
+__device__ bool get_slot(const uint64_t *s, uint64_t gen, uint64_t &p1, uint64_t &p2,
+                         const Instance &I, Control *ctl, uint64_t timeout) {
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t it = 1;; ++it) {
+        const uint64_t a = __hip_atomic_load(s + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t b = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t c = __hip_atomic_load(s + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((a & 0xFFFFull) == gen && (b & 0xFFFFull) == gen && (c & 0xFFFFull) == gen) {
+            p1 = (a & ~0xFFFFull) | ((b >> 16) & 0xFFFFull);
+            p2 = c & ~0xFFFFull;
+            return true;
+        }
+        if ((it & 63u) == 0) {
+            if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+            if (wall_clock64() - t0 > timeout) {
+                atomicOr(&ctl->error, kErrTimeout);
+                atomicOr(I.status, kErrTimeout);
+                __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
             }
         }
-        if (failed) break;
-        m1 = umin64(m1, (a & ~0xFFFFull) | ((b >> 16) & 0xFFFFull));
-        m2 = umin64(m2, c & ~0xFFFFull);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    uint64_t f = failed ? 0 : kEmpty;  // any failure -> 0 after the min
-    uint64_t dummy = kEmpty;
-    block_min2(f, dummy);
-    block_min2(m1, m2);
+}
+
+// Publish this workgroup's candidates for generation `epoch`, wait for the
+// rest of the group, and return the group-wide minima (Section 5.3 steps
+// 2-4: every processor ends up with the same global minimum).  Returns false
+// if the wait was abandoned; the decision is the same for every thread.
+__device__ bool group_exchange(const Instance &I, int g, int w, uint32_t epoch, uint64_t &p1,
+                               uint64_t &p2, Control *ctl, uint64_t timeout) {
+    if (threadIdx.x == 0) s_fail = 0;
+    block_min2(p1, p2);
+    const uint64_t gen = epoch & 0xFFFFu;
+    uint64_t *base = I.slots + (size_t)(epoch & 1u) * (g + 1) * kSlotStride;
+    if (threadIdx.x == 0) {
+        // Everything this workgroup wrote before the barrier in block_min2
+        // becomes visible to whoever observes the slot.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        put_slot(base + (size_t)w * kSlotStride, p1, p2, gen);
+    }
+    uint64_t m1 = kEmpty, m2 = kEmpty;
+    if (I.exchange == kExchAllToAll || w == 0) {
+        for (int t = threadIdx.x; t < g; t += kBlock) {
+            uint64_t a1, a2;
+            if (!get_slot(base + (size_t)t * kSlotStride, gen, a1, a2, I, ctl, timeout)) {
+                atomicOr(&s_fail, 1u);
+                break;
+            }
+            m1 = umin64(m1, a1);
+            m2 = umin64(m2, a2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        block_min2(m1, m2);
+        if (I.exchange == kExchReducer && threadIdx.x == 0 && !s_fail) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            put_slot(base + (size_t)g * kSlotStride, m1, m2, gen);
+        }
+    } else {
+        if (threadIdx.x == 0) {
+            if (!get_slot(base + (size_t)g * kSlotStride, gen, m1, m2, I, ctl, timeout)) s_fail = 1;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        block_min2(m1, m2);
+    }
     p1 = m1;
     p2 = m2;
-    return f != 0;
+    return s_fail == 0;
 }
 
 // Run one instance on workgroup w of a group of g.
@@ -305,6 +375,7 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
     L.tile = reinterpret_cast<float *>(L.amask + mask_words);
     float *D = I.D;
 
+    if (tid == 0) st.mark = wall_clock64();
     for (int li = tid; li < own_cap; li += kBlock) L.cache[li] = kEmptyRow;
     for (int q = tid; q < mask_words; q += kBlock) {
         int rem = n - q * 32;
@@ -329,6 +400,7 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
             p1 = umin64(p1, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
     }
 
+    st.lap(kPhSetup);
     int i_prev = -1;
     // Size of the cluster formed by the previous merge.  Every workgroup
     // carries it in a register; its owner writes it to gsize one merge later,
@@ -341,6 +413,7 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
         } else {
             block_min2(p1, p2);
         }
+        st.lap(s == 0 ? kPhSetup : kPhWait);
         if (s == 0) {
             // Set-up results (input check) are visible to everyone now; thread 0
             // reads the status word and the decision is shared through LDS so
@@ -464,6 +537,8 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
         }
         __syncthreads();
 
+        st.lap(kPhUpdate);
+
         // ---- refresh rows whose cached partner is gone --------------------
         const uint32_t nresc = s_nresc;
         for (uint32_t r = 0; r < nresc; ++r) {
@@ -478,6 +553,8 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
         if (tid == 0) st.rescans += nresc;
         __syncthreads();
 
+        st.lap(kPhRescan);
+
         // ---- local candidates for the next argmin -------------------------
         p1 = kEmpty;
         for (int li = tid; li < own_ch * 64; li += kBlock) {
@@ -489,6 +566,7 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
         }
         i_prev = i;
         last_size = ni + nj;
+        st.lap(kPhCand);
     }
 }
 
@@ -500,6 +578,10 @@ __device__ void flush_stats(Control *ctl, Stats &st) {
         atomicAdd(&ctl->rescans, a);
         atomicAdd(&ctl->rescan_elems, b);
         atomicAdd(&ctl->update_elems, c);
+        for (int p = 0; p < kPhases; ++p) {
+            atomicAdd(&ctl->prof_sum[p], st.prof[p]);
+            atomicMax(&ctl->prof_max[p], st.prof[p]);
+        }
     }
 }
 
