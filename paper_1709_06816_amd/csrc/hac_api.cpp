@@ -17,6 +17,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultSingleWgN = 2048;
+constexpr int kDefaultWorkgroups = 16;
 constexpr int64_t kDefaultTimeoutMs = 10000;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -302,29 +303,30 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     c->stats = hac_stats{};
     if (n == 1) return HAC_OK;
 
-    // Launch shape: one workgroup for small n, else a co-resident group.
+    // Launch shape: one workgroup for small n, else a co-resident group of
+    // a few large workgroups (each merge costs every workgroup one agent-scope
+    // release/acquire pair, so fewer workgroups mean a cheaper exchange).
     const int nch = (n + 63) / 64;
     const int single_n = c->opt_single_n > 0 ? (int)c->opt_single_n : kDefaultSingleWgN;
     int g = 1;
-    if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1)) > c->lds_max) {
-        int want = c->opt_wgs > 0 ? (int)c->opt_wgs : c->cus;
+    if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1), false) > c->lds_max) {
+        int want = c->opt_wgs > 0 ? (int)c->opt_wgs : kDefaultWorkgroups;
         g = std::max(1, std::min(want, nch));
-        while (g < nch && hac::lds_bytes(n, hac::own_rows(n, g)) > c->lds_max) ++g;
-        const size_t lds = hac::lds_bytes(n, hac::own_rows(n, g));
+        while (g < nch && hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max) ++g;
+        const size_t lds = hac::lds_bytes(n, hac::own_rows(n, g), false);
         if (lds > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit in LDS", n);
         const int cap = max_coresident(c, lds);
         if (g > cap) g = cap;
-        if (hac::lds_bytes(n, hac::own_rows(n, g)) > c->lds_max)
+        if (hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max)
             return fail(c, HAC_EDEVICE, "n=%d needs more co-resident workgroups than the device holds", n);
-        if (!c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
-        if (g < 2) g = 1;
+        if (g > 1 && !c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
     }
 
-    // Workspace: control | status | sizes | slots.
+    // Workspace: control | status | first row minima | slots.
     const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
     const size_t st_off = ctl_bytes, st_bytes = kAlign;
-    const size_t gs_off = st_off + st_bytes, gs_bytes = align_up((size_t)n * 4, kAlign);
-    const size_t sl_off = gs_off + gs_bytes;
+    const size_t rk_off = st_off + st_bytes, rk_bytes = align_up((size_t)n * 8, kAlign);
+    const size_t sl_off = rk_off + rk_bytes;
     const size_t sl_bytes = g > 1 ? (size_t)2 * (g + 1) * hac::kSlotStride * 8 : 0;
     rc = ensure_dev(c, &c->ws, &c->ws_cap, sl_off + sl_bytes, "workspace");
     if (rc) return rc;
@@ -352,7 +354,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     hac::Instance inst;
     inst.D = D;
     inst.out = dev_out;
-    inst.gsize = reinterpret_cast<int32_t *>(ws + gs_off);
+    inst.rowkey = reinterpret_cast<uint64_t *>(ws + rk_off);
     inst.slots = reinterpret_cast<uint64_t *>(ws + sl_off);
     inst.status = reinterpret_cast<uint32_t *>(ws + st_off);
     inst.n = n;
@@ -364,8 +366,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
     if (sl_bytes) HIP_TRY(c, hac::launch_zero(ws + sl_off, sl_bytes / 4, s));
-    HIP_TRY(c, hipEventRecord(c->ev[1], s));
-    hipError_t e = hac::launch_run(inst, g, ctl, timeout_ticks(c), s);
+    hipError_t e = hac::launch_run(inst, g, ctl, timeout_ticks(c), s, c->ev[1]);
     if (e != hipSuccess) return hip_fail(c, e, "merge kernel launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     c->pending_wgs = g;
@@ -393,7 +394,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         rec_extent = std::max(rec_extent, out_offsets[k] + (int64_t)ns[k] - 1);
         nmax = std::max(nmax, (int)ns[k]);
     }
-    const size_t lds = hac::lds_bytes(nmax, hac::own_rows(nmax, 1));
+    const size_t lds = hac::lds_bytes(nmax, hac::own_rows(nmax, 1), true);
     if (lds > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit one workgroup's LDS", nmax);
     int rc = set_device(c);
     if (rc) return rc;
@@ -439,7 +440,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         hac::Instance &I = hin[k];
         I.D = base + offsets[k];
         I.out = dev_out + out_offsets[k];
-        I.gsize = nullptr;
+        I.rowkey = nullptr;
         I.slots = nullptr;
         I.status = reinterpret_cast<uint32_t *>(ws + st_off) + k;
         I.n = ns[k];

@@ -8,8 +8,9 @@
 
 namespace hac {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
-constexpr int kWaves = kBlock / 64;
+constexpr int kRunBlock = 1024;      // threads per workgroup of the single-instance kernel
+constexpr int kBatchBlock = 256;     // threads per workgroup of the batch kernel
+constexpr int kSetupBlock = 256;     // threads per workgroup of the set-up kernel
 constexpr int kChunk = 64;           // rows owned in chunks of 64 (one wave's lanes)
 constexpr int kTile = 64;            // mirror tile edge
 constexpr int kSlotStride = 512;     // u64 words between exchange slots (4 KiB)
@@ -46,7 +47,7 @@ struct Control {
 struct Instance {
     float *D;            // working matrix, n x n, leading dimension n
     hac_merge *out;      // n-1 records (device)
-    int32_t *gsize;      // cluster sizes, n entries (used when g > 1)
+    uint64_t *rowkey;    // n first row minima from the set-up kernel (single-instance path)
     uint64_t *slots;     // exchange slots: 2 * (g + 1) * kSlotStride words (g > 1)
     uint32_t *status;    // per-instance kErr* word
     int32_t n;
@@ -55,19 +56,20 @@ struct Instance {
     int32_t pad;
 };
 
-// Bytes of dynamic LDS one workgroup needs to own `own` rows of an n-item
-// instance.
-size_t lds_bytes(int n, int own);
 // Rows a workgroup owns when g workgroups share n items.
 int own_rows(int n, int g);
+// Bytes of dynamic LDS one workgroup needs to own `own` rows of an n-item
+// instance; `in_kernel_setup` adds room for the mirror tile (batch kernel).
+size_t lds_bytes(int n, int own, bool in_kernel_setup);
 
 // Fill `words` u32 with zero on `stream` (a kernel, not a memset node).
 hipError_t launch_zero(void *p, size_t words, hipStream_t stream);
 
-// One instance on g workgroups (g > 1 uses a cooperative launch so that all
-// are co-resident).
+// Single instance: set-up kernel over the whole device, then the merge kernel
+// on g workgroups (g > 1 uses a cooperative launch so that all are
+// co-resident).  `setup_done` is recorded on the stream between the two.
 hipError_t launch_run(const Instance &inst, int g, Control *ctl, uint64_t timeout_ticks,
-                      hipStream_t stream);
+                      hipStream_t stream, hipEvent_t setup_done);
 
 // `count` instances, one workgroup each, taken in the order of `order`
 // (device int32[count]) from a queue; grid workgroups.

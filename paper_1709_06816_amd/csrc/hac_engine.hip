@@ -1,36 +1,44 @@
 // Device engine: Lance-Williams agglomerative clustering on gfx950.
 //
-// One instance is run by a group of g workgroups (g = 1 for small and batched
-// instances; g up to the number of co-resident workgroups for large ones).
-// All n-1 merges of an instance happen inside one launch.
+// Three kernels:
+//   k_setup   (single-instance path) validates and canonicalises the strict
+//             upper triangle, mirrors it into the lower triangle and writes
+//             each row's first cached minimum; it spreads the O(n^2) pass over
+//             the whole device.
+//   k_run     runs all n-1 merges of one instance on a group of g co-resident
+//             workgroups of 1024 threads (g = 1 for small n).
+//   k_batch   runs many independent instances, one workgroup of 256 threads
+//             each, taken largest-first from a queue; each workgroup does its
+//             instance's set-up itself.
 //
-// Work split (one GPU, the whole matrix in HBM):
-//   * The n x n fp32 matrix is kept fully symmetric, row-major.  Rows are
-//     owned in chunks of 64 by the group's workgroups (boustrophedon order so
-//     that the triangular set-up work is balanced).
-//   * Each workgroup keeps, in LDS, a cache entry per owned row k:
-//     (ord(min_{l>k live} D[k][l]) : 32 | argmin l : 16 | size(k)-1 : 16),
-//     i.e. the row's closest live partner to its right with ties to the
-//     smallest l, plus the cluster size.
-//   * Merge step (Section 4 steps 1-4; Section 5.3 steps 1-6):
-//       argmin   every workgroup publishes the smallest cached key of its
-//                rows and the smallest new entry of row i (see below); the
-//                group minimum is the lexicographically smallest (D, i, j),
-//                the same on every workgroup, so no second broadcast is
-//                needed (Section 5.3, steps 2-5).
-//       update   the owner of column k reads D[i][k], D[j][k] (coalesced row
-//                reads), applies the Table 1 update, writes D[i][k] (row) and
-//                D[k][i] (column, through symmetric storage), refreshes its
-//                cache entry for row k and queues a rescan of row k when the
-//                cached partner was i or j and can no longer be trusted
-//                (Section 5.3, step 6).
-//       row i    its new minimum over l > i is reduced from the updated
-//                values themselves and carried in the next exchange.
-//   * Exchange between workgroups: each workgroup writes three 64-bit words
-//     tagged with a 16-bit generation into its own slot (double-buffered by
-//     parity) after an agent-scope release fence; every workgroup polls all
-//     slots of the group and takes an agent-scope acquire fence.  One
-//     exchange per merge, no atomic counter.
+// Data layout (one GPU, the whole matrix in HBM):
+//   * The n x n fp32 matrix is kept fully symmetric, row-major, so that both
+//     D[i][k] and D[k][i] of the merged row/column are reachable with
+//     coalesced row accesses (Section 5.2 stores only the upper half, split
+//     over processors; here both halves live in one HBM).
+//   * Rows are owned in chunks of 64 by the group's workgroups (boustrophedon
+//     order over rounds of g chunks).  Each workgroup keeps, in LDS, a cache
+//     entry per owned row k: ord(min_{l>k live} D[k][l]) : 32 | argmin l : 16
+//     (ties to the smallest l), a live bitmask of all slots and the size of
+//     every cluster (every workgroup applies the same size updates).
+//
+// One merge (Section 4 steps 1-4; Section 5.3 steps 1-6):
+//   argmin   every workgroup publishes the smallest cached key of its rows and
+//            the smallest new entry of the previous survivor's row; the group
+//            minimum is the lexicographically smallest (D, i, j) and is the
+//            same on every workgroup, so no second broadcast is needed
+//            (steps 2-5 of Section 5.3).
+//   update   the owner of column k reads D[i][k], D[j][k] (row reads),
+//            applies the Table 1 update, writes D[i][k] (row) and D[k][i]
+//            (column, through symmetric storage), refreshes its cache entry
+//            for row k, and queues a rescan of row k when the cached partner
+//            was i or j and the new value cannot replace it (step 6).
+//   row i    its new minimum over l > i is reduced from the new values
+//            themselves and carried in the next exchange.
+// Exchange between workgroups: each workgroup writes three 64-bit words
+// tagged with a 16-bit generation into its own slot (double-buffered by
+// parity) after an agent-scope release fence; readers poll the slots and take
+// an agent-scope acquire fence.  One exchange per merge.
 #include <hip/hip_runtime.h>
 
 #include "hac_engine.h"
@@ -42,8 +50,12 @@ constexpr uint64_t kEmpty = ~0ull;                     // "no candidate"
 constexpr uint32_t kEmptyOrd = 0xFFFFFFFFu;             // above ord(+inf)
 constexpr uint64_t kEmptyRow = 0xFFFFFFFFFFFF0000ull;   // cache entry without partner
 constexpr uint64_t kHi32 = 0xFFFFFFFF00000000ull;
-constexpr int kUpdBatch = 8;                           // chunks per wave per load batch
-constexpr int kScanUnroll = 8;                         // loads in flight per thread in a rescan
+constexpr int kMaxWaves = 16;
+// Loads in flight per thread: chunks per wave per update batch, and 16-byte
+// loads per rescan step.  Large workgroups need fewer per thread for the same
+// bytes in flight and have only 128 VGPRs per thread.
+template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
+template <int B> constexpr int scan_unroll() { return B >= 1024 ? 4 : 8; }
 
 // Order-preserving map of fp32 onto u32 (zeros are canonical +0 here).
 __device__ __forceinline__ uint32_t ord32(float x) {
@@ -108,21 +120,19 @@ __device__ __forceinline__ int own_chunks(int n, int g, int w) {
     int last = (full & 1) ? (g - 1 - w) : w;
     return full + (last < rem ? 1 : 0);
 }
+__device__ __forceinline__ int row_of_local(int li, int g, int w) {
+    return chunk_of(li >> 6, g, w) * 64 + (li & 63);
+}
 
-struct Lds {
-    uint64_t *cache;    // own_cap entries
-    uint16_t *rlist;    // own_cap entries: rows queued for a rescan (local index)
-    uint32_t *amask;    // live bitmask of all n slots
-    float *tile;        // kTile x (kTile + 1), set-up only
-};
-
-__shared__ uint64_t s_red[2][kWaves];
+__shared__ uint64_t s_red[2][kMaxWaves];
 __shared__ uint32_t s_nresc;
-__shared__ int s_inst;
 __shared__ uint32_t s_fail;
+__shared__ int s_inst;
 
 // Minimum of (a, b) over the workgroup, returned to every thread.
+template <int B>
 __device__ void block_min2(uint64_t &a, uint64_t &b) {
+    constexpr int W = B / 64;
     a = wave_min(a);
     b = wave_min(b);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -135,13 +145,15 @@ __device__ void block_min2(uint64_t &a, uint64_t &b) {
     a = s_red[0][0];
     b = s_red[1][0];
 #pragma unroll
-    for (int q = 1; q < kWaves; ++q) {
+    for (int q = 1; q < W; ++q) {
         a = umin64(a, s_red[0][q]);
         b = umin64(b, s_red[1][q]);
     }
 }
 
+template <int B>
 __device__ unsigned long long block_sum(unsigned long long v) {
+    constexpr int W = B / 64;
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
@@ -149,13 +161,14 @@ __device__ unsigned long long block_sum(unsigned long long v) {
     __syncthreads();
     unsigned long long r = 0;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) r += s_red[0][q];
+    for (int q = 0; q < W; ++q) r += s_red[0][q];
     return r;
 }
 
 // Smallest (D[k][l], l) over live l > k; kEmpty if none.  Whole workgroup.
 // `elems` counts the live entries this thread compared.  Rows are read with
 // 16-byte loads when n is a multiple of 4 (row starts are then aligned).
+template <int B>
 __device__ uint64_t rescan_row(const float *__restrict__ D, int n, int k, const uint32_t *amask,
                                unsigned long long &elems) {
     const float *row = D + (size_t)k * n;
@@ -163,16 +176,17 @@ __device__ uint64_t rescan_row(const float *__restrict__ D, int n, int k, const 
     if ((n & 3) == 0) {
         const float4 *r4 = reinterpret_cast<const float4 *>(row);
         const int nq = n >> 2;
-        for (int q0 = ((k + 1) >> 2) + (int)threadIdx.x; q0 < nq; q0 += kScanUnroll * kBlock) {
+        constexpr int kScanUnroll = scan_unroll<B>();
+        for (int q0 = ((k + 1) >> 2) + (int)threadIdx.x; q0 < nq; q0 += kScanUnroll * B) {
             float4 x[kScanUnroll];
 #pragma unroll
             for (int u = 0; u < kScanUnroll; ++u) {
-                const int q = q0 + u * kBlock;
+                const int q = q0 + u * B;
                 x[u] = q < nq ? r4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
 #pragma unroll
             for (int u = 0; u < kScanUnroll; ++u) {
-                const int q = q0 + u * kBlock;
+                const int q = q0 + u * B;
                 if (q >= nq) continue;
                 // live bits of l = 4q .. 4q+3, restricted to l > k
                 uint32_t m = (amask[q >> 3] >> ((q & 7) * 4)) & 0xFu;
@@ -188,16 +202,17 @@ __device__ uint64_t rescan_row(const float *__restrict__ D, int n, int k, const 
             }
         }
     } else {
-        for (int l0 = k + 1 + (int)threadIdx.x; l0 < n; l0 += kScanUnroll * kBlock) {
+        constexpr int kScanUnroll = scan_unroll<B>();
+        for (int l0 = k + 1 + (int)threadIdx.x; l0 < n; l0 += kScanUnroll * B) {
             float x[kScanUnroll];
 #pragma unroll
             for (int u = 0; u < kScanUnroll; ++u) {
-                int l = l0 + u * kBlock;
+                int l = l0 + u * B;
                 x[u] = l < n ? row[l] : 0.0f;
             }
 #pragma unroll
             for (int u = 0; u < kScanUnroll; ++u) {
-                int l = l0 + u * kBlock;
+                int l = l0 + u * B;
                 if (l < n && is_live(amask, l)) {
                     best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
                     ++elems;
@@ -206,62 +221,59 @@ __device__ uint64_t rescan_row(const float *__restrict__ D, int n, int k, const 
         }
     }
     uint64_t dummy = kEmpty;
-    block_min2(best, dummy);
+    block_min2<B>(best, dummy);
     return best;
 }
 
-// Set-up (plays the part of the paper's initial distribution of the matrix):
-// validate and canonicalise the strict upper triangle, mirror it into the
-// lower triangle, and compute each owned row's first cache entry.  The owner
-// of row block R handles every tile (R, C >= R), so row minima stay in LDS.
-__device__ void setup_rows(const Instance &I, int g, int w, Lds &L) {
-    const int n = I.n, T = (n + 63) >> 6;
+// Set-up of row block R (rows 64R .. 64R+63), playing the part of the
+// paper's initial distribution of the matrix: for every tile (R, C >= R)
+// validate and canonicalise the strict-upper entries, mirror them into tile
+// (C, R), and keep each row's running minimum.  Hands the minimum key
+// (ord : 32 | column : 16) of row 64R + r to `sink(r, key)` (lane 0 of the
+// wave holding that row; kEmpty if the row has no entry to its right).
+template <int B, class Sink>
+__device__ void setup_block(float *D, int n, int R, float *tile, uint32_t &bad, Sink sink) {
+    constexpr int W = B / 64, P = 64 / W;  // rows of a tile per wave
+    const int T = (n + 63) >> 6;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float *D = I.D;
-    uint32_t bad = 0;
-    for (int lq = 0;; ++lq) {
-        const int R = chunk_of(lq, g, w);
-        if (R >= T) break;
-        uint64_t run[16];
+    uint64_t run[P];
 #pragma unroll
-        for (int p = 0; p < 16; ++p) run[p] = kEmpty;
-        for (int C = R; C < T; ++C) {
-            float x[16];
-            const int col = C * 64 + lane;
+    for (int p = 0; p < P; ++p) run[p] = kEmpty;
+    for (int C = R; C < T; ++C) {
+        float x[P];
+        const int col = C * 64 + lane;
 #pragma unroll
-            for (int p = 0; p < 16; ++p) {
-                const int row = R * 64 + wv + 4 * p;
-                x[p] = (row < n && col < n && col > row) ? D[(size_t)row * n + col] : 0.0f;
-            }
+        for (int p = 0; p < P; ++p) {
+            const int row = R * 64 + wv + W * p;
+            x[p] = (row < n && col < n && col > row) ? D[(size_t)row * n + col] : 0.0f;
+        }
 #pragma unroll
-            for (int p = 0; p < 16; ++p) {
-                const int rr = wv + 4 * p, row = R * 64 + rr;
-                if (row < n && col < n && col > row) {
-                    if (!(fabsf(x[p]) <= 0x1p100f)) bad = 1;
-                    if (__float_as_uint(x[p]) == 0x80000000u) {
-                        x[p] = 0.0f;
-                        D[(size_t)row * n + col] = 0.0f;
-                    }
-                    run[p] = umin64(run[p], ((uint64_t)ord32(x[p]) << 32) | ((uint64_t)col << 16));
+        for (int p = 0; p < P; ++p) {
+            const int rr = wv + W * p, row = R * 64 + rr;
+            if (row < n && col < n && col > row) {
+                if (!(fabsf(x[p]) <= 0x1p100f)) bad = 1;
+                if (__float_as_uint(x[p]) == 0x80000000u) {
+                    x[p] = 0.0f;
+                    D[(size_t)row * n + col] = 0.0f;
                 }
-                L.tile[rr * (kTile + 1) + lane] = x[p];
+                run[p] = umin64(run[p], ((uint64_t)ord32(x[p]) << 32) | ((uint64_t)col << 16));
             }
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < 16; ++p) {
-                const int a = wv + 4 * p;  // row inside the lower tile (C, R)
-                const int lrow = C * 64 + a, lcol = R * 64 + lane;
-                if (lrow < n && lcol < lrow) D[(size_t)lrow * n + lcol] = L.tile[lane * (kTile + 1) + a];
-            }
-            __syncthreads();
+            tile[rr * (kTile + 1) + lane] = x[p];
         }
+        __syncthreads();
 #pragma unroll
-        for (int p = 0; p < 16; ++p) {
-            uint64_t v = wave_min(run[p]);
-            if (lane == 0) L.cache[lq * 64 + wv + 4 * p] = (v == kEmpty) ? kEmptyRow : v;
+        for (int p = 0; p < P; ++p) {
+            const int a = wv + W * p;  // row inside the lower tile (C, R)
+            const int lrow = C * 64 + a, lcol = R * 64 + lane;
+            if (lrow < n && lcol < lrow) D[(size_t)lrow * n + lcol] = tile[lane * (kTile + 1) + a];
         }
+        __syncthreads();
     }
-    if (bad) atomicOr(I.status, kErrInput);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint64_t v = wave_min(run[p]);
+        if (lane == 0) sink(wv + W * p, v);
+    }
 }
 
 struct Stats {
@@ -319,10 +331,11 @@ __device__ bool get_slot(const uint64_t *s, uint64_t gen, uint64_t &p1, uint64_t
 // rest of the group, and return the group-wide minima (Section 5.3 steps
 // 2-4: every processor ends up with the same global minimum).  Returns false
 // if the wait was abandoned; the decision is the same for every thread.
+template <int B>
 __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t epoch, uint64_t &p1,
                                uint64_t &p2, Control *ctl, uint64_t timeout) {
     if (threadIdx.x == 0) s_fail = 0;
-    block_min2(p1, p2);
+    block_min2<B>(p1, p2);
     const uint64_t gen = epoch & 0xFFFFu;
     uint64_t *base = I.slots + (size_t)(epoch & 1u) * (g + 1) * kSlotStride;
     if (threadIdx.x == 0) {
@@ -333,17 +346,21 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t epoch, 
     }
     uint64_t m1 = kEmpty, m2 = kEmpty;
     if (I.exchange == kExchAllToAll || w == 0) {
-        for (int t = threadIdx.x; t < g; t += kBlock) {
-            uint64_t a1, a2;
-            if (!get_slot(base + (size_t)t * kSlotStride, gen, a1, a2, I, ctl, timeout)) {
-                atomicOr(&s_fail, 1u);
-                break;
+        if ((int)threadIdx.x < g) {
+            for (int t = threadIdx.x; t < g; t += B) {
+                uint64_t a1, a2;
+                if (!get_slot(base + (size_t)t * kSlotStride, gen, a1, a2, I, ctl, timeout)) {
+                    atomicOr(&s_fail, 1u);
+                    break;
+                }
+                m1 = umin64(m1, a1);
+                m2 = umin64(m2, a2);
             }
-            m1 = umin64(m1, a1);
-            m2 = umin64(m2, a2);
+            // Only the polling waves take the acquire; the barrier below
+            // orders the other waves' later loads after it.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        block_min2(m1, m2);
+        block_min2<B>(m1, m2);
         if (I.exchange == kExchReducer && threadIdx.x == 0 && !s_fail) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             put_slot(base + (size_t)g * kSlotStride, m1, m2, gen);
@@ -353,87 +370,78 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t epoch, 
             if (!get_slot(base + (size_t)g * kSlotStride, gen, m1, m2, I, ctl, timeout)) s_fail = 1;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        block_min2(m1, m2);
+        block_min2<B>(m1, m2);
     }
     p1 = m1;
     p2 = m2;
     return s_fail == 0;
 }
 
-// Run one instance on workgroup w of a group of g.
-__device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Control *ctl,
-                             uint64_t timeout, Stats &st) {
-    const int n = I.n, link = I.link;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
-    const int own_ch = own_chunks(n, g, w);
-    const int own_cap = ((((n + 63) >> 6) + g - 1) / g) * 64;
-    const int mask_words = (n + 31) >> 5;
+// LDS of one workgroup.
+struct Lds {
+    uint64_t *cache;    // own_cap entries: ord:32 | partner:16 | 0:16
+    uint16_t *rlist;    // own_cap entries: rows queued for a rescan (local index)
+    uint32_t *amask;    // live bitmask of all n slots
+    uint16_t *size1;    // size - 1 of every slot's cluster (n entries)
+    float *tile;        // mirror tile (in-kernel set-up only; shares space with size1)
+};
+
+__device__ Lds carve(uint8_t *smem, int n, int own_cap) {
     Lds L;
     L.cache = reinterpret_cast<uint64_t *>(smem);
     L.rlist = reinterpret_cast<uint16_t *>(L.cache + own_cap);
     L.amask = reinterpret_cast<uint32_t *>(L.rlist + own_cap);
-    L.tile = reinterpret_cast<float *>(L.amask + mask_words);
-    float *D = I.D;
+    L.size1 = reinterpret_cast<uint16_t *>(L.amask + (((n + 31) >> 5) + 3) / 4 * 4);
+    L.tile = reinterpret_cast<float *>(L.size1);
+    return L;
+}
 
-    if (tid == 0) st.mark = wall_clock64();
-    for (int li = tid; li < own_cap; li += kBlock) L.cache[li] = kEmptyRow;
-    for (int q = tid; q < mask_words; q += kBlock) {
-        int rem = n - q * 32;
+template <int B>
+__device__ void init_masks(const Lds &L, int n) {
+    const int mask_words = (n + 31) >> 5;
+    for (int q = threadIdx.x; q < mask_words; q += B) {
+        const int rem = n - q * 32;
         L.amask[q] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
     }
-    __syncthreads();
-    setup_rows(I, g, w, L);
-    if (g > 1) {
-        for (int li = tid; li < own_ch * 64; li += kBlock) {
-            int k = chunk_of(li >> 6, g, w) * 64 + (li & 63);
-            if (k < n) I.gsize[k] = 1;
-        }
-    }
-    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += B) L.size1[k] = 0;
+}
 
-    // Local candidates: smallest cached key of the owned rows, none for row i.
+// All n-1 merges of one instance on workgroup w of a group of g.  On entry
+// the cache holds every owned row's first minimum, the masks are initialised
+// and the input is known to be valid.
+template <int B>
+__device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
+                           uint64_t timeout, Stats &st) {
+    constexpr int W = B / 64;
+    constexpr int kUpdBatch = upd_batch<B>();
+    const int n = I.n, link = I.link;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+    const int own_ch = own_chunks(n, g, w);
+    float *D = I.D;
+
+    // Local candidates: smallest cached key of the owned rows.
     uint64_t p1 = kEmpty, p2 = kEmpty;
-    for (int li = tid; li < own_ch * 64; li += kBlock) {
-        int k = chunk_of(li >> 6, g, w) * 64 + (li & 63);
-        uint64_t c = L.cache[li];
-        if (k < n && (c >> 32) != kEmptyOrd)
+    for (int li = tid; li < own_ch * 64; li += B) {
+        const int k = row_of_local(li, g, w);
+        const uint64_t c = L.cache[li];
+        if (k < n && (uint32_t)(c >> 32) != kEmptyOrd)
             p1 = umin64(p1, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
     }
-
-    st.lap(kPhSetup);
+    if (tid == 0) s_nresc = 0;
     int i_prev = -1;
-    // Size of the cluster formed by the previous merge.  Every workgroup
-    // carries it in a register; its owner writes it to gsize one merge later,
-    // when no workgroup can still be reading the old value.
-    int last_size = 0;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
         if (g > 1) {
-            if (!group_exchange(I, g, w, (uint32_t)s + 1u, p1, p2, ctl, timeout)) return;
+            if (!group_exchange<B>(I, g, w, (uint32_t)s + 1u, p1, p2, ctl, timeout)) return;
         } else {
-            block_min2(p1, p2);
+            block_min2<B>(p1, p2);
         }
         st.lap(s == 0 ? kPhSetup : kPhWait);
-        if (s == 0) {
-            // Set-up results (input check) are visible to everyone now; thread 0
-            // reads the status word and the decision is shared through LDS so
-            // that every thread leaves together.
-            uint64_t ok = kEmpty, dummy = kEmpty;
-            if (tid == 0 &&
-                (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput))
-                ok = 0;
-            block_min2(ok, dummy);
-            if (ok == 0) return;
-        }
         uint64_t key_ip = kEmpty;
         if (i_prev >= 0 && (uint32_t)(p2 >> 32) != kEmptyOrd)
             key_ip = (p2 & kHi32) | ((uint64_t)i_prev << 16) | ((p2 >> 16) & 0xFFFFull);
-        if (i_prev >= 0 && owner_of_row(i_prev, g) == w && tid == 0) {
-            const int li = local_of_row(i_prev, g);
-            const uint64_t c = L.cache[li];
-            L.cache[li] = (((uint32_t)(p2 >> 32) != kEmptyOrd) ? (p2 & ~0xFFFFull) : kEmptyRow) |
-                          (c & 0xFFFFull);
-        }
+        if (i_prev >= 0 && tid == 0 && owner_of_row(i_prev, g) == w)
+            L.cache[local_of_row(i_prev, g)] = ((uint32_t)(p2 >> 32) != kEmptyOrd) ? p2 : kEmptyRow;
         const uint64_t win = umin64(p1, key_ip);
         if ((uint32_t)(win >> 32) == kEmptyOrd) {
             if (tid == 0) {
@@ -446,18 +454,7 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
         const int i = (int)((win >> 16) & 0xFFFFull);
         const int j = (int)(win & 0xFFFFull);
         const float h = unord32((uint32_t)(win >> 32));
-        int ni, nj;
-        if (g == 1) {
-            // The size bits of row i may have just been rewritten by thread 0.
-            __syncthreads();
-            ni = (int)(L.cache[i] & 0xFFFFull) + 1;
-            nj = (int)(L.cache[j] & 0xFFFFull) + 1;
-        } else {
-            ni = i == i_prev ? last_size
-                             : __hip_atomic_load(I.gsize + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            nj = j == i_prev ? last_size
-                             : __hip_atomic_load(I.gsize + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        const int ni = (int)L.size1[i] + 1, nj = (int)L.size1[j] + 1;
         // ---- output the level (Section 4 step 4) -------------------------
         if (w == 0 && tid == 0) {
             int4 rec;
@@ -468,21 +465,7 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
             reinterpret_cast<int4 *>(I.out)[s] = rec;
         }
         if (s == n - 2) break;
-
-        // ---- bookkeeping: j retired, i grows (Section 5.3 step 6) ---------
-        if (tid == 0) {
-            L.amask[j >> 5] &= ~(1u << (j & 31));
-            s_nresc = 0;
-            if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
-            if (owner_of_row(i, g) == w) {
-                const int li = local_of_row(i, g);
-                L.cache[li] = (L.cache[li] & ~0xFFFFull) | (uint64_t)(ni + nj - 1);
-            }
-            // Other workgroups read gsize[i] for this merge; the new size of i
-            // is published during the next one (they use last_size meanwhile).
-            if (g > 1 && i_prev >= 0 && owner_of_row(i_prev, g) == w) I.gsize[i_prev] = last_size;
-        }
-        __syncthreads();
+        __syncthreads();  // cache[i_prev] written; size1[i], size1[j] read by all
 
         // ---- Lance-Williams update of row/column i (Section 4 step 3) -----
         float ai = 0.0f, aj = 0.0f;
@@ -494,11 +477,11 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
         float *Di = D + (size_t)i * n;
         const float *Dj = D + (size_t)j * n;
         p2 = kEmpty;
-        for (int lq0 = wv; lq0 < own_ch; lq0 += kWaves * kUpdBatch) {
+        for (int lq0 = wv; lq0 < own_ch; lq0 += W * kUpdBatch) {
             float a[kUpdBatch], b[kUpdBatch];
 #pragma unroll
             for (int u = 0; u < kUpdBatch; ++u) {
-                const int lq = lq0 + u * kWaves;
+                const int lq = lq0 + u * W;
                 const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
                 const bool ok = k < n;
                 a[u] = ok ? Di[k] : 0.0f;
@@ -506,13 +489,13 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
             }
 #pragma unroll
             for (int u = 0; u < kUpdBatch; ++u) {
-                const int lq = lq0 + u * kWaves;
+                const int lq = lq0 + u * W;
                 if (lq >= own_ch) break;
                 const int k = chunk_of(lq, g, w) * 64 + lane;
                 if (k >= n || k == i || k == j || !is_live(L.amask, k)) continue;
                 const int li = lq * 64 + lane;
                 const uint64_t c = L.cache[li];
-                const int nk = (int)(c & 0xFFFFull) + 1;
+                const int nk = (int)L.size1[k] + 1;
                 const float v = lw_update(link, a[u], b[u], h, ni, nj, nk, ai, aj);
                 Di[k] = v;
                 D[(size_t)k * n + i] = v;
@@ -524,11 +507,11 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
                     const uint32_t oc = (uint32_t)(c >> 32);
                     if (nn == i || nn == j) {
                         if (ov <= oc)
-                            L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16) | (c & 0xFFFFull);
+                            L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16);
                         else
                             L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
                     } else if (ov < oc || (ov == oc && i < nn)) {
-                        L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16) | (c & 0xFFFFull);
+                        L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16);
                     }
                 } else if (k < j && nn == j) {
                     L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
@@ -536,44 +519,50 @@ __device__ void run_instance(const Instance &I, int g, int w, uint8_t *smem, Con
             }
         }
         __syncthreads();
-
+        // ---- bookkeeping: j retired, i grows (Section 5.3 step 6) ---------
+        if (tid == 0) {
+            L.amask[j >> 5] &= ~(1u << (j & 31));
+            L.size1[i] = (uint16_t)(ni + nj - 1);
+            if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
+        }
+        __syncthreads();
         st.lap(kPhUpdate);
 
         // ---- refresh rows whose cached partner is gone --------------------
         const uint32_t nresc = s_nresc;
         for (uint32_t r = 0; r < nresc; ++r) {
             const int li = L.rlist[r];
-            const int k = chunk_of(li >> 6, g, w) * 64 + (li & 63);
-            const uint64_t best = rescan_row(D, n, k, L.amask, st.rescan_elems);
-            if (tid == 0) {
-                const uint64_t c = L.cache[li];
-                L.cache[li] = (best == kEmpty ? kEmptyRow : best) | (c & 0xFFFFull);
-            }
+            const uint64_t best = rescan_row<B>(D, n, row_of_local(li, g, w), L.amask, st.rescan_elems);
+            if (tid == 0) L.cache[li] = best == kEmpty ? kEmptyRow : best;
         }
-        if (tid == 0) st.rescans += nresc;
-        __syncthreads();
-
+        if (nresc) {
+            if (tid == 0) {
+                st.rescans += nresc;
+                s_nresc = 0;
+            }
+            __syncthreads();
+        }
         st.lap(kPhRescan);
 
         // ---- local candidates for the next argmin -------------------------
         p1 = kEmpty;
-        for (int li = tid; li < own_ch * 64; li += kBlock) {
-            const int k = chunk_of(li >> 6, g, w) * 64 + (li & 63);
+        for (int li = tid; li < own_ch * 64; li += B) {
+            const int k = row_of_local(li, g, w);
             if (k >= n || k == i) continue;
             const uint64_t c = L.cache[li];
             if ((uint32_t)(c >> 32) == kEmptyOrd) continue;
             p1 = umin64(p1, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
         }
         i_prev = i;
-        last_size = ni + nj;
         st.lap(kPhCand);
     }
 }
 
+template <int B>
 __device__ void flush_stats(Control *ctl, Stats &st) {
-    unsigned long long a = block_sum(st.rescans);
-    unsigned long long b = block_sum(st.rescan_elems);
-    unsigned long long c = block_sum(st.update_elems);
+    unsigned long long a = block_sum<B>(st.rescans);
+    unsigned long long b = block_sum<B>(st.rescan_elems);
+    unsigned long long c = block_sum<B>(st.update_elems);
     if (threadIdx.x == 0) {
         atomicAdd(&ctl->rescans, a);
         atomicAdd(&ctl->rescan_elems, b);
@@ -585,16 +574,48 @@ __device__ void flush_stats(Control *ctl, Stats &st) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_run(Instance inst, Control *ctl, uint64_t timeout) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    Stats st;
-    run_instance(inst, (int)gridDim.x, (int)blockIdx.x, smem, ctl, timeout, st);
-    flush_stats(ctl, st);
+// Set-up for the single-instance path: workgroup b handles row blocks b and
+// T-1-b (equal numbers of tiles), writing each row's first minimum to rowkey.
+__global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I) {
+    __shared__ float tile[kTile * (kTile + 1)];
+    const int n = I.n, T = (n + 63) >> 6;
+    const int b = (int)blockIdx.x;
+    uint32_t bad = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int R = pass == 0 ? b : T - 1 - b;
+        if (pass == 1 && R == b) break;
+        setup_block<kSetupBlock>(I.D, n, R, tile, bad, [&](int r, uint64_t v) {
+            const int row = R * 64 + r;
+            if (row < n) I.rowkey[row] = v == kEmpty ? kEmptyRow : v;
+        });
+    }
+    if (bad) atomicOr(I.status, kErrInput);
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch(const Instance *__restrict__ insts,
-                                                 const int32_t *__restrict__ order, int count,
-                                                 Control *ctl, uint64_t timeout) {
+__global__ __launch_bounds__(kRunBlock) void k_run(Instance I, Control *ctl, uint64_t timeout) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    Stats st;
+    if (threadIdx.x == 0) st.mark = wall_clock64();
+    const int g = (int)gridDim.x, w = (int)blockIdx.x, n = I.n;
+    const int own_cap = ((((n + 63) >> 6) + g - 1) / g) * 64;
+    const Lds L = carve(smem, n, own_cap);
+    // The set-up kernel has finished: its status word is final and the same
+    // for every thread of every workgroup.
+    if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
+    init_masks<kRunBlock>(L, n);
+    const int own_ch = own_chunks(n, g, w);
+    for (int li = threadIdx.x; li < own_cap; li += kRunBlock) {
+        const int k = row_of_local(li, g, w);
+        L.cache[li] = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmptyRow;
+    }
+    __syncthreads();
+    merge_loop<kRunBlock>(I, g, w, L, ctl, timeout, st);
+    flush_stats<kRunBlock>(ctl, st);
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batch(const Instance *__restrict__ insts,
+                                                      const int32_t *__restrict__ order, int count,
+                                                      Control *ctl, uint64_t timeout) {
     extern __shared__ __align__(16) uint8_t smem[];
     Stats st;
     for (;;) {
@@ -603,11 +624,32 @@ __global__ __launch_bounds__(kBlock) void k_batch(const Instance *__restrict__ i
         const int q = s_inst;
         __syncthreads();
         if (q >= count) break;
-        const Instance inst = insts[order[q]];
-        if (inst.n > 1) run_instance(inst, 1, 0, smem, ctl, timeout, st);
+        const Instance I = insts[order[q]];
+        const int n = I.n;
+        if (n < 2) continue;
+        if (threadIdx.x == 0) st.mark = wall_clock64();
+        const int nch = (n + 63) >> 6;
+        const Lds L = carve(smem, n, nch * 64);
+        for (int li = threadIdx.x; li < nch * 64; li += kBatchBlock) L.cache[li] = kEmptyRow;
+        __syncthreads();
+        uint32_t bad = 0;
+        for (int R = 0; R < nch; ++R)
+            setup_block<kBatchBlock>(I.D, n, R, L.tile, bad, [&](int r, uint64_t v) {
+                L.cache[R * 64 + r] = v == kEmpty ? kEmptyRow : v;
+            });
+        // Every thread's verdict on the input, shared through LDS.
+        uint64_t okv = bad ? 0 : kEmpty, dummy = kEmpty;
+        block_min2<kBatchBlock>(okv, dummy);
+        if (okv == 0) {
+            if (threadIdx.x == 0) atomicOr(I.status, kErrInput);
+            continue;
+        }
+        init_masks<kBatchBlock>(L, n);  // size1 shares space with the tile
+        __syncthreads();
+        merge_loop<kBatchBlock>(I, 1, 0, L, ctl, timeout, st);
         __syncthreads();
     }
-    flush_stats(ctl, st);
+    flush_stats<kBatchBlock>(ctl, st);
 }
 
 __global__ void k_zero(uint32_t *p, size_t words) {
@@ -620,22 +662,25 @@ __global__ void k_zero(uint32_t *p, size_t words) {
 
 int own_rows(int n, int g) { return ((((n + 63) >> 6) + g - 1) / g) * 64; }
 
-size_t lds_bytes(int n, int own) {
-    const size_t mask_words = (size_t)(n + 31) / 32;
-    return (size_t)own * 8 + (size_t)own * 2 + mask_words * 4 + (size_t)kTile * (kTile + 1) * 4;
+size_t lds_bytes(int n, int own, bool in_kernel_setup) {
+    const size_t mask = (((size_t)(n + 31) / 32 + 3) / 4 * 4) * 4;
+    const size_t size1 = (size_t)n * 2;
+    const size_t tile = in_kernel_setup ? (size_t)kTile * (kTile + 1) * 4 : 0;
+    return (size_t)own * 8 + (size_t)own * 2 + mask + (size1 > tile ? size1 : tile);
 }
 
 hipError_t engine_setup(size_t max_lds, size_t *usable) {
     // Dynamic LDS may use what the static LDS of the kernels leaves free.
     size_t static_max = 0;
-    for (const void *fn : {reinterpret_cast<const void *>(&k_run), reinterpret_cast<const void *>(&k_batch)}) {
+    const void *fns[] = {reinterpret_cast<const void *>(&k_run), reinterpret_cast<const void *>(&k_batch)};
+    for (const void *fn : fns) {
         hipFuncAttributes a;
         hipError_t e = hipFuncGetAttributes(&a, fn);
         if (e != hipSuccess) return e;
         static_max = a.sharedSizeBytes > static_max ? a.sharedSizeBytes : static_max;
     }
     const size_t dyn = max_lds > static_max ? max_lds - static_max : 0;
-    for (const void *fn : {reinterpret_cast<const void *>(&k_run), reinterpret_cast<const void *>(&k_batch)}) {
+    for (const void *fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
         if (e != hipSuccess) return e;
     }
@@ -646,7 +691,8 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
 int engine_occupancy(size_t lds, bool batch) {
     int blocks = 0;
     const void *fn = batch ? reinterpret_cast<const void *>(&k_batch) : reinterpret_cast<const void *>(&k_run);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, lds) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, batch ? kBatchBlock : kRunBlock, lds) !=
+        hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
@@ -662,23 +708,31 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream) {
 }
 
 hipError_t launch_run(const Instance &inst, int g, Control *ctl, uint64_t timeout_ticks,
-                      hipStream_t stream) {
-    const size_t lds = lds_bytes(inst.n, own_rows(inst.n, g));
+                      hipStream_t stream, hipEvent_t setup_done) {
+    const int T = (inst.n + 63) / 64;
+    hipLaunchKernelGGL(k_setup, dim3((T + 1) / 2), dim3(kSetupBlock), 0, stream, inst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (setup_done) {
+        e = hipEventRecord(setup_done, stream);
+        if (e != hipSuccess) return e;
+    }
+    const size_t lds = lds_bytes(inst.n, own_rows(inst.n, g), false);
     if (g == 1) {
-        hipLaunchKernelGGL(k_run, dim3(1), dim3(kBlock), lds, stream, inst, ctl, timeout_ticks);
+        hipLaunchKernelGGL(k_run, dim3(1), dim3(kRunBlock), lds, stream, inst, ctl, timeout_ticks);
         return hipGetLastError();
     }
     Instance a0 = inst;
     Control *a1 = ctl;
     uint64_t a2 = timeout_ticks;
     void *args[] = {&a0, &a1, &a2};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_run), dim3(g), dim3(kBlock),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_run), dim3(g), dim3(kRunBlock),
                                       args, (unsigned)lds, stream);
 }
 
 hipError_t launch_batch(const Instance *insts, const int32_t *order, int count, int grid,
                         size_t lds, Control *ctl, uint64_t timeout_ticks, hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBlock), lds, stream, insts, order, count, ctl,
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchBlock), lds, stream, insts, order, count, ctl,
                        timeout_ticks);
     return hipGetLastError();
 }
