@@ -90,17 +90,15 @@ __device__ __forceinline__ float lw_update(int link, float dki, float dkj, float
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
-__device__ __forceinline__ uint64_t wave_min(uint64_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off, 64));
-    return v;
-}
+// Wave-wide reductions from the ROCm device library (DPP lane moves, no LDS
+// round trips); the result is uniform across the wave.  Call with every lane
+// of the wave active.
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_min_u64(unsigned long long);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
 
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ uint64_t wave_min(uint64_t v) { return __ockl_wfred_min_u64(v); }
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) { return __ockl_wfred_add_u64(v); }
 
 __device__ __forceinline__ bool is_live(const uint32_t *amask, int l) {
     return (amask[l >> 5] >> (l & 31)) & 1u;
@@ -437,11 +435,12 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             block_min2<B>(p1, p2);
         }
         st.lap(s == 0 ? kPhSetup : kPhWait);
+        // Row i_prev's new cache entry: its smallest new value to the right.
+        // The thread that owns it in the update below stores it.
+        const uint64_t ip_entry = ((uint32_t)(p2 >> 32) != kEmptyOrd) ? p2 : kEmptyRow;
         uint64_t key_ip = kEmpty;
         if (i_prev >= 0 && (uint32_t)(p2 >> 32) != kEmptyOrd)
             key_ip = (p2 & kHi32) | ((uint64_t)i_prev << 16) | ((p2 >> 16) & 0xFFFFull);
-        if (i_prev >= 0 && tid == 0 && owner_of_row(i_prev, g) == w)
-            L.cache[local_of_row(i_prev, g)] = ((uint32_t)(p2 >> 32) != kEmptyOrd) ? p2 : kEmptyRow;
         const uint64_t win = umin64(p1, key_ip);
         if ((uint32_t)(win >> 32) == kEmptyOrd) {
             if (tid == 0) {
@@ -465,7 +464,12 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             reinterpret_cast<int4 *>(I.out)[s] = rec;
         }
         if (s == n - 2) break;
-        __syncthreads();  // cache[i_prev] written; size1[i], size1[j] read by all
+        // Slot j is retired (Section 5.3 step 6).  Other threads test other
+        // bits of the same mask word meanwhile, hence the atomic.
+        if (tid == 0) {
+            atomicAnd(&L.amask[j >> 5], ~(1u << (j & 31)));
+            if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
+        }
 
         // ---- Lance-Williams update of row/column i (Section 4 step 3) -----
         float ai = 0.0f, aj = 0.0f;
@@ -494,7 +498,8 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 const int k = chunk_of(lq, g, w) * 64 + lane;
                 if (k >= n || k == i || k == j || !is_live(L.amask, k)) continue;
                 const int li = lq * 64 + lane;
-                const uint64_t c = L.cache[li];
+                const uint64_t c = k == i_prev ? ip_entry : L.cache[li];
+                if (k == i_prev) L.cache[li] = ip_entry;
                 const int nk = (int)L.size1[k] + 1;
                 const float v = lw_update(link, a[u], b[u], h, ni, nj, nk, ai, aj);
                 Di[k] = v;
@@ -519,13 +524,9 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             }
         }
         __syncthreads();
-        // ---- bookkeeping: j retired, i grows (Section 5.3 step 6) ---------
-        if (tid == 0) {
-            L.amask[j >> 5] &= ~(1u << (j & 31));
-            L.size1[i] = (uint16_t)(ni + nj - 1);
-            if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
-        }
-        __syncthreads();
+        // Cluster i grows; every thread has read size1[i] and size1[j] for
+        // this merge, and nothing reads them again before the next one.
+        if (tid == 0) L.size1[i] = (uint16_t)(ni + nj - 1);
         st.lap(kPhUpdate);
 
         // ---- refresh rows whose cached partner is gone --------------------
