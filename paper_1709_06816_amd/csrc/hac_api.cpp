@@ -44,7 +44,7 @@ struct hac_ctx {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 
     hac_stats stats{};
-    int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0, opt_exchange = 0;
+    int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0, opt_exchange = 0, opt_profile = 0;
 
     // State of the last enqueued call, for hac_sync / stats.
     bool pending = false;
@@ -260,6 +260,7 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
     case HAC_OPT_WORKGROUPS: c->opt_wgs = value; return HAC_OK;
     case HAC_OPT_SINGLE_WG_N: c->opt_single_n = value; return HAC_OK;
     case HAC_OPT_TIMEOUT_MS: c->opt_timeout_ms = value; return HAC_OK;
+    case HAC_OPT_PROFILE: c->opt_profile = value != 0; return HAC_OK;
     case HAC_OPT_EXCHANGE:
         if (value > 1) return fail(c, HAC_EINVAL, "exchange mode %lld", (long long)value);
         c->opt_exchange = value;
@@ -360,7 +361,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     inst.n = n;
     inst.link = linkage;
     inst.exchange = (int32_t)c->opt_exchange;
-    inst.pad = 0;
+    inst.flags = c->opt_profile ? hac::kFlagProfile : 0;
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
@@ -446,7 +447,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         I.n = ns[k];
         I.link = linkages[k];
         I.exchange = 0;
-        I.pad = 0;
+        I.flags = c->opt_profile ? hac::kFlagProfile : 0;
     }
     std::vector<int32_t> ord(count);
     std::iota(ord.begin(), ord.end(), 0);

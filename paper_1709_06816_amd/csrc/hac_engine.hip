@@ -55,7 +55,7 @@ constexpr int kMaxWaves = 16;
 // loads per rescan step.  Large workgroups need fewer per thread for the same
 // bytes in flight and have only 128 VGPRs per thread.
 template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
-template <int B> constexpr int scan_unroll() { return B >= 1024 ? 4 : 8; }
+template <int B> constexpr int seg_unroll() { return 8; }
 
 // Order-preserving map of fp32 onto u32 (zeros are canonical +0 here).
 __device__ __forceinline__ uint32_t ord32(float x) {
@@ -100,6 +100,30 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v) { return __ockl_wfred_m
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) { return __ockl_wfred_add_u64(v); }
 
+// 64-bit value of the lane picked by DPP control CTRL (all lanes active).
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Minimum over each group of four lanes (quad_perm [1,0,3,2] then [2,3,0,1]).
+__device__ __forceinline__ uint64_t quad_min(uint64_t v) {
+    v = umin64(v, dpp_u64<0xB1>(v));
+    return umin64(v, dpp_u64<0x4E>(v));
+}
+
+// Fold every lane's v into the LDS word *acc: a quad reduction, then one
+// atomic minimum per group of four lanes.  Call with every lane of the wave
+// active.
+__device__ __forceinline__ void lds_min(uint64_t *acc, uint64_t v) {
+    v = quad_min(v);
+    if ((threadIdx.x & 3) == 0 && v != ~0ull)
+        atomicMin(reinterpret_cast<unsigned long long *>(acc), (unsigned long long)v);
+}
+
+
 __device__ __forceinline__ bool is_live(const uint32_t *amask, int l) {
     return (amask[l >> 5] >> (l & 31)) & 1u;
 }
@@ -123,6 +147,10 @@ __device__ __forceinline__ int row_of_local(int li, int g, int w) {
 }
 
 __shared__ uint64_t s_red[2][kMaxWaves];
+// Per-epoch accumulators, double-buffered by epoch parity:
+// [0] smallest cached key of this workgroup's rows, [1] smallest new entry of
+// the survivor's row, [2] and [3] the same minima over the whole group.
+__shared__ uint64_t s_acc[2][4];
 __shared__ uint32_t s_nresc;
 __shared__ uint32_t s_fail;
 __shared__ int s_inst;
@@ -161,66 +189,6 @@ __device__ unsigned long long block_sum(unsigned long long v) {
 #pragma unroll
     for (int q = 0; q < W; ++q) r += s_red[0][q];
     return r;
-}
-
-// Smallest (D[k][l], l) over live l > k; kEmpty if none.  Whole workgroup.
-// `elems` counts the live entries this thread compared.  Rows are read with
-// 16-byte loads when n is a multiple of 4 (row starts are then aligned).
-template <int B>
-__device__ uint64_t rescan_row(const float *__restrict__ D, int n, int k, const uint32_t *amask,
-                               unsigned long long &elems) {
-    const float *row = D + (size_t)k * n;
-    uint64_t best = kEmpty;
-    if ((n & 3) == 0) {
-        const float4 *r4 = reinterpret_cast<const float4 *>(row);
-        const int nq = n >> 2;
-        constexpr int kScanUnroll = scan_unroll<B>();
-        for (int q0 = ((k + 1) >> 2) + (int)threadIdx.x; q0 < nq; q0 += kScanUnroll * B) {
-            float4 x[kScanUnroll];
-#pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) {
-                const int q = q0 + u * B;
-                x[u] = q < nq ? r4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            }
-#pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) {
-                const int q = q0 + u * B;
-                if (q >= nq) continue;
-                // live bits of l = 4q .. 4q+3, restricted to l > k
-                uint32_t m = (amask[q >> 3] >> ((q & 7) * 4)) & 0xFu;
-                const int below = k + 1 - 4 * q;  // entries l < k+1 inside this quad
-                if (below > 0) m &= (0xFu << below) & 0xFu;
-                if (!m) continue;
-                elems += __popc(m);
-                const float v[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if ((m >> c) & 1u)
-                        best = umin64(best, ((uint64_t)ord32(v[c]) << 32) | ((uint64_t)(4 * q + c) << 16));
-            }
-        }
-    } else {
-        constexpr int kScanUnroll = scan_unroll<B>();
-        for (int l0 = k + 1 + (int)threadIdx.x; l0 < n; l0 += kScanUnroll * B) {
-            float x[kScanUnroll];
-#pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) {
-                int l = l0 + u * B;
-                x[u] = l < n ? row[l] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) {
-                int l = l0 + u * B;
-                if (l < n && is_live(amask, l)) {
-                    best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
-                    ++elems;
-                }
-            }
-        }
-    }
-    uint64_t dummy = kEmpty;
-    block_min2<B>(best, dummy);
-    return best;
 }
 
 // Set-up of row block R (rows 64R .. 64R+63), playing the part of the
@@ -325,27 +293,28 @@ __device__ bool get_slot(const uint64_t *s, uint64_t gen, uint64_t &p1, uint64_t
     }
 }
 
-// Publish this workgroup's candidates for generation `epoch`, wait for the
-// rest of the group, and return the group-wide minima (Section 5.3 steps
-// 2-4: every processor ends up with the same global minimum).  Returns false
-// if the wait was abandoned; the decision is the same for every thread.
+// Publish this workgroup's candidates of epoch e (s_acc[e&1][0..1]), wait for
+// the rest of the group, and leave the group-wide minima in s_acc[e&1][2..3]
+// (Section 5.3 steps 2-4: every processor ends up with the same global
+// minimum).  Ends with a barrier.  Returns false if the wait was abandoned;
+// the decision is the same for every thread.
 template <int B>
-__device__ bool group_exchange(const Instance &I, int g, int w, uint32_t epoch, uint64_t &p1,
-                               uint64_t &p2, Control *ctl, uint64_t timeout) {
-    if (threadIdx.x == 0) s_fail = 0;
-    block_min2<B>(p1, p2);
-    const uint64_t gen = epoch & 0xFFFFu;
-    uint64_t *base = I.slots + (size_t)(epoch & 1u) * (g + 1) * kSlotStride;
+__device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Control *ctl,
+                               uint64_t timeout) {
+    const int b = e & 1;
+    const uint64_t gen = e & 0xFFFFu;
+    uint64_t *base = I.slots + (size_t)b * (g + 1) * kSlotStride;
     if (threadIdx.x == 0) {
-        // Everything this workgroup wrote before the barrier in block_min2
-        // becomes visible to whoever observes the slot.
+        s_fail = 0;
+        // Everything this workgroup wrote before the last barrier becomes
+        // visible to whoever observes the slot.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        put_slot(base + (size_t)w * kSlotStride, p1, p2, gen);
+        put_slot(base + (size_t)w * kSlotStride, s_acc[b][0], s_acc[b][1], gen);
     }
-    uint64_t m1 = kEmpty, m2 = kEmpty;
     if (I.exchange == kExchAllToAll || w == 0) {
-        if ((int)threadIdx.x < g) {
-            for (int t = threadIdx.x; t < g; t += B) {
+        if (threadIdx.x < 64) {  // wave 0 polls: lane t reads slots t, t+64, ...
+            uint64_t m1 = kEmpty, m2 = kEmpty;
+            for (int t = threadIdx.x; t < g; t += 64) {
                 uint64_t a1, a2;
                 if (!get_slot(base + (size_t)t * kSlotStride, gen, a1, a2, I, ctl, timeout)) {
                     atomicOr(&s_fail, 1u);
@@ -354,24 +323,26 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t epoch, 
                 m1 = umin64(m1, a1);
                 m2 = umin64(m2, a2);
             }
-            // Only the polling waves take the acquire; the barrier below
-            // orders the other waves' later loads after it.
+            // The barrier below orders the other waves' later loads after this.
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            lds_min(&s_acc[b][2], m1);
+            lds_min(&s_acc[b][3], m2);
         }
-        block_min2<B>(m1, m2);
+        __syncthreads();
         if (I.exchange == kExchReducer && threadIdx.x == 0 && !s_fail) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            put_slot(base + (size_t)g * kSlotStride, m1, m2, gen);
+            put_slot(base + (size_t)g * kSlotStride, s_acc[b][2], s_acc[b][3], gen);
         }
     } else {
         if (threadIdx.x == 0) {
+            uint64_t m1 = kEmpty, m2 = kEmpty;
             if (!get_slot(base + (size_t)g * kSlotStride, gen, m1, m2, I, ctl, timeout)) s_fail = 1;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_acc[b][2] = m1;
+            s_acc[b][3] = m2;
         }
-        block_min2<B>(m1, m2);
+        __syncthreads();
     }
-    p1 = m1;
-    p2 = m2;
     return s_fail == 0;
 }
 
@@ -404,6 +375,92 @@ __device__ void init_masks(const Lds &L, int n) {
     for (int k = threadIdx.x; k < n; k += B) L.size1[k] = 0;
 }
 
+// Recompute the cache entries of the rows queued in rlist (their entries were
+// set to kEmptyRow when queued): each becomes the smallest (D[k][l], l) over
+// live l > k.  Row tails are cut into segments of one wave's loads; the waves
+// take segments round-robin across all queued rows and fold their lanes'
+// minima into the entry with LDS atomics, so no barrier is needed per row.
+template <int B>
+__device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, const Lds &L,
+                            uint32_t nresc, unsigned long long &elems) {
+    constexpr int W = B / 64, U = seg_unroll<B>();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int base = 0;
+    for (uint32_t r = 0; r < nresc; ++r) {
+        const int li = L.rlist[r];
+        const int k = row_of_local(li, g, w);
+        const float *row = D + (size_t)k * n;
+        const int first_sg = ((wv - base) % W + W) % W;
+        int nseg;
+        if ((n & 3) == 0) {
+            // 16-byte loads over quads q0 .. n/4-1; row starts are aligned.
+            const float4 *r4 = reinterpret_cast<const float4 *>(row);
+            const int q0 = (k + 1) >> 2, nq = n >> 2;
+            nseg = (nq - q0 + 64 * U - 1) / (64 * U);
+            for (int sg = first_sg; sg < nseg; sg += W) {
+                float4 x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = q0 + sg * 64 * U + u * 64 + lane;
+                    x[u] = q < nq ? r4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
+                uint64_t best = kEmpty;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = q0 + sg * 64 * U + u * 64 + lane;
+                    if (q >= nq) continue;
+                    uint32_t m = (L.amask[q >> 3] >> ((q & 7) * 4)) & 0xFu;  // live l = 4q..4q+3
+                    const int below = k + 1 - 4 * q;                           // those with l <= k
+                    if (below > 0) m &= (0xFu << below) & 0xFu;
+                    elems += __popc(m);
+                    const float v[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if ((m >> c) & 1u)
+                            best = umin64(best, ((uint64_t)ord32(v[c]) << 32) | ((uint64_t)(4 * q + c) << 16));
+                }
+                lds_min(&L.cache[li], best);
+            }
+        } else {
+            const int l0 = k + 1;
+            nseg = (n - l0 + 64 * U - 1) / (64 * U);
+            for (int sg = first_sg; sg < nseg; sg += W) {
+                float x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int l = l0 + sg * 64 * U + u * 64 + lane;
+                    x[u] = l < n ? row[l] : 0.0f;
+                }
+                uint64_t best = kEmpty;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int l = l0 + sg * 64 * U + u * 64 + lane;
+                    if (l < n && is_live(L.amask, l)) {
+                        best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
+                        ++elems;
+                    }
+                }
+                lds_min(&L.cache[li], best);
+            }
+        }
+        base += nseg;
+    }
+}
+
+// Fold the smallest cached key (ord:32 | row:16 | partner:16) of this
+// workgroup's live rows other than `skip` into *acc.
+template <int B>
+__device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, int skip, uint64_t *acc) {
+    uint64_t p = kEmpty;
+    for (int li = threadIdx.x; li < own_ch * 64; li += B) {
+        const int k = row_of_local(li, g, w);
+        const uint64_t c = L.cache[li];
+        if (k < n && k != skip && (uint32_t)(c >> 32) != kEmptyOrd)
+            p = umin64(p, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
+    }
+    lds_min(acc, p);
+}
+
 // All n-1 merges of one instance on workgroup w of a group of g.  On entry
 // the cache holds every owned row's first minimum, the masks are initialised
 // and the input is known to be valid.
@@ -415,26 +472,36 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     const int n = I.n, link = I.link;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
     const int own_ch = own_chunks(n, g, w);
+    const bool prof = (I.flags & kFlagProfile) != 0;
     float *D = I.D;
 
-    // Local candidates: smallest cached key of the owned rows.
-    uint64_t p1 = kEmpty, p2 = kEmpty;
-    for (int li = tid; li < own_ch * 64; li += B) {
-        const int k = row_of_local(li, g, w);
-        const uint64_t c = L.cache[li];
-        if (k < n && (uint32_t)(c >> 32) != kEmptyOrd)
-            p1 = umin64(p1, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
+    if (tid == 0) {
+        for (int b = 0; b < 2; ++b)
+            for (int q = 0; q < 4; ++q) s_acc[b][q] = kEmpty;
+        s_nresc = 0;
     }
-    if (tid == 0) s_nresc = 0;
+    __syncthreads();
+    fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[1][0]);  // candidates of epoch 1
     int i_prev = -1;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
+        const uint32_t e = (uint32_t)s + 1u;
+        const int b = e & 1;
+        // The other parity's accumulators were last read before the last
+        // barrier of the previous merge; clear them for epoch e+1.
+        if (tid == 0)
+            for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;
+        __syncthreads();
+        uint64_t p1, p2;
         if (g > 1) {
-            if (!group_exchange<B>(I, g, w, (uint32_t)s + 1u, p1, p2, ctl, timeout)) return;
+            if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+            p1 = s_acc[b][2];
+            p2 = s_acc[b][3];
         } else {
-            block_min2<B>(p1, p2);
+            p1 = s_acc[b][0];
+            p2 = s_acc[b][1];
         }
-        st.lap(s == 0 ? kPhSetup : kPhWait);
+        if (prof) st.lap(s == 0 ? kPhSetup : kPhWait);
         // Row i_prev's new cache entry: its smallest new value to the right.
         // The thread that owns it in the update below stores it.
         const uint64_t ip_entry = ((uint32_t)(p2 >> 32) != kEmptyOrd) ? p2 : kEmptyRow;
@@ -480,16 +547,16 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         }
         float *Di = D + (size_t)i * n;
         const float *Dj = D + (size_t)j * n;
-        p2 = kEmpty;
+        uint64_t q2 = kEmpty;
         for (int lq0 = wv; lq0 < own_ch; lq0 += W * kUpdBatch) {
-            float a[kUpdBatch], b[kUpdBatch];
+            float a[kUpdBatch], bv[kUpdBatch];
 #pragma unroll
             for (int u = 0; u < kUpdBatch; ++u) {
                 const int lq = lq0 + u * W;
                 const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
                 const bool ok = k < n;
                 a[u] = ok ? Di[k] : 0.0f;
-                b[u] = ok ? Dj[k] : 0.0f;
+                bv[u] = ok ? Dj[k] : 0.0f;
             }
 #pragma unroll
             for (int u = 0; u < kUpdBatch; ++u) {
@@ -501,61 +568,56 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 const uint64_t c = k == i_prev ? ip_entry : L.cache[li];
                 if (k == i_prev) L.cache[li] = ip_entry;
                 const int nk = (int)L.size1[k] + 1;
-                const float v = lw_update(link, a[u], b[u], h, ni, nj, nk, ai, aj);
+                const float v = lw_update(link, a[u], bv[u], h, ni, nj, nk, ai, aj);
                 Di[k] = v;
                 D[(size_t)k * n + i] = v;
                 st.update_elems++;
                 const uint32_t ov = ord32(v);
-                if (k > i) p2 = umin64(p2, ((uint64_t)ov << 32) | ((uint64_t)k << 16));
+                if (k > i) q2 = umin64(q2, ((uint64_t)ov << 32) | ((uint64_t)k << 16));
                 const int nn = (int)((c >> 16) & 0xFFFFull);
+                bool requeue = false;
                 if (k < i) {
                     const uint32_t oc = (uint32_t)(c >> 32);
                     if (nn == i || nn == j) {
                         if (ov <= oc)
                             L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16);
                         else
-                            L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
+                            requeue = true;
                     } else if (ov < oc || (ov == oc && i < nn)) {
                         L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16);
                     }
                 } else if (k < j && nn == j) {
+                    requeue = true;
+                }
+                if (requeue) {
+                    L.cache[li] = kEmptyRow;  // rebuilt by the rescan below
                     L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
                 }
             }
         }
+        lds_min(&s_acc[b ^ 1][1], q2);  // row i's candidates for epoch e+1
         __syncthreads();
         // Cluster i grows; every thread has read size1[i] and size1[j] for
         // this merge, and nothing reads them again before the next one.
         if (tid == 0) L.size1[i] = (uint16_t)(ni + nj - 1);
-        st.lap(kPhUpdate);
+        if (prof) st.lap(kPhUpdate);
 
         // ---- refresh rows whose cached partner is gone --------------------
         const uint32_t nresc = s_nresc;
-        for (uint32_t r = 0; r < nresc; ++r) {
-            const int li = L.rlist[r];
-            const uint64_t best = rescan_row<B>(D, n, row_of_local(li, g, w), L.amask, st.rescan_elems);
-            if (tid == 0) L.cache[li] = best == kEmpty ? kEmptyRow : best;
-        }
         if (nresc) {
+            rescan_rows<B>(D, n, g, w, L, nresc, st.rescan_elems);
+            __syncthreads();
             if (tid == 0) {
                 st.rescans += nresc;
                 s_nresc = 0;
             }
-            __syncthreads();
         }
-        st.lap(kPhRescan);
+        if (prof) st.lap(kPhRescan);
 
         // ---- local candidates for the next argmin -------------------------
-        p1 = kEmpty;
-        for (int li = tid; li < own_ch * 64; li += B) {
-            const int k = row_of_local(li, g, w);
-            if (k >= n || k == i) continue;
-            const uint64_t c = L.cache[li];
-            if ((uint32_t)(c >> 32) == kEmptyOrd) continue;
-            p1 = umin64(p1, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
-        }
+        fold_candidates<B>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
         i_prev = i;
-        st.lap(kPhCand);
+        if (prof) st.lap(kPhCand);
     }
 }
 
@@ -596,7 +658,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I) {
 __global__ __launch_bounds__(kRunBlock) void k_run(Instance I, Control *ctl, uint64_t timeout) {
     extern __shared__ __align__(16) uint8_t smem[];
     Stats st;
-    if (threadIdx.x == 0) st.mark = wall_clock64();
+    if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
     const int g = (int)gridDim.x, w = (int)blockIdx.x, n = I.n;
     const int own_cap = ((((n + 63) >> 6) + g - 1) / g) * 64;
     const Lds L = carve(smem, n, own_cap);
@@ -628,7 +690,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const Instance *__restric
         const Instance I = insts[order[q]];
         const int n = I.n;
         if (n < 2) continue;
-        if (threadIdx.x == 0) st.mark = wall_clock64();
+        if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
         const int nch = (n + 63) >> 6;
         const Lds L = carve(smem, n, nch * 64);
         for (int li = threadIdx.x; li < nch * 64; li += kBatchBlock) L.cache[li] = kEmptyRow;
