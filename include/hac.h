@@ -139,13 +139,16 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        1 = workgroup 0 reads them and broadcasts the minimum
  *   HAC_OPT_PROFILE      1 = time the phases of the merge loop on the device
  *                        (reported in hac_stats.phase_*; adds ~0.5 us per merge)
+ *   HAC_OPT_BLOCK        threads per workgroup of hac_run: 256, 512 or 1024
+ *                        (0 = automatic)
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
     HAC_OPT_SINGLE_WG_N = 2,
     HAC_OPT_TIMEOUT_MS = 3,
     HAC_OPT_EXCHANGE = 4,
-    HAC_OPT_PROFILE = 5
+    HAC_OPT_PROFILE = 5,
+    HAC_OPT_BLOCK = 6
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 

@@ -33,7 +33,7 @@ HAC_OK, HAC_EINVAL, HAC_EINPUT, HAC_ENOMEM, HAC_EDEVICE, HAC_ENODEV, HAC_EBUSY, 
     HAC_ETIMEDOUT, HAC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PRESERVE_INPUT = 1
 OUT_DEVICE = 2
-OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE, OPT_PROFILE = 1, 2, 3, 4, 5
+OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE, OPT_PROFILE, OPT_BLOCK = 1, 2, 3, 4, 5, 6
 MAX_N = 65536
 MAX_BATCH_N = 8192
 

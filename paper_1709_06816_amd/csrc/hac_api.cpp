@@ -45,6 +45,7 @@ struct hac_ctx {
 
     hac_stats stats{};
     int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0, opt_exchange = 0, opt_profile = 0;
+    int64_t opt_block = 0;
 
     // State of the last enqueued call, for hac_sync / stats.
     bool pending = false;
@@ -134,8 +135,8 @@ uint64_t timeout_ticks(const hac_ctx *c) {
 }
 
 // Workgroups that can be co-resident for a hac_run launch with `lds` bytes.
-int max_coresident(hac_ctx *c, size_t lds) {
-    int per_cu = hac::engine_occupancy(lds, false);
+int max_coresident(hac_ctx *c, size_t lds, int block) {
+    int per_cu = hac::engine_occupancy(lds, block);
     if (per_cu < 1) per_cu = 1;
     return per_cu * c->cus;
 }
@@ -261,6 +262,11 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
     case HAC_OPT_SINGLE_WG_N: c->opt_single_n = value; return HAC_OK;
     case HAC_OPT_TIMEOUT_MS: c->opt_timeout_ms = value; return HAC_OK;
     case HAC_OPT_PROFILE: c->opt_profile = value != 0; return HAC_OK;
+    case HAC_OPT_BLOCK:
+        if (value != 0 && value != 256 && value != 512 && value != 1024)
+            return fail(c, HAC_EINVAL, "block size %lld is not 256, 512 or 1024", (long long)value);
+        c->opt_block = value;
+        return HAC_OK;
     case HAC_OPT_EXCHANGE:
         if (value > 1) return fail(c, HAC_EINVAL, "exchange mode %lld", (long long)value);
         c->opt_exchange = value;
@@ -308,6 +314,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     // a few large workgroups (each merge costs every workgroup one agent-scope
     // release/acquire pair, so fewer workgroups mean a cheaper exchange).
     const int nch = (n + 63) / 64;
+    const int block = c->opt_block > 0 ? (int)c->opt_block : hac::kRunBlock;
     const int single_n = c->opt_single_n > 0 ? (int)c->opt_single_n : kDefaultSingleWgN;
     int g = 1;
     if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1), false) > c->lds_max) {
@@ -316,7 +323,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
         while (g < nch && hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max) ++g;
         const size_t lds = hac::lds_bytes(n, hac::own_rows(n, g), false);
         if (lds > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit in LDS", n);
-        const int cap = max_coresident(c, lds);
+        const int cap = max_coresident(c, lds, block);
         if (g > cap) g = cap;
         if (hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max)
             return fail(c, HAC_EDEVICE, "n=%d needs more co-resident workgroups than the device holds", n);
@@ -367,7 +374,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
     if (sl_bytes) HIP_TRY(c, hac::launch_zero(ws + sl_off, sl_bytes / 4, s));
-    hipError_t e = hac::launch_run(inst, g, ctl, timeout_ticks(c), s, c->ev[1]);
+    hipError_t e = hac::launch_run(inst, g, block, ctl, timeout_ticks(c), s, c->ev[1]);
     if (e != hipSuccess) return hip_fail(c, e, "merge kernel launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     c->pending_wgs = g;
@@ -459,7 +466,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
     HIP_TRY(c, hipEventRecord(c->ev[1], s));
-    int per_cu = std::max(1, hac::engine_occupancy(lds, true));
+    int per_cu = std::max(1, hac::engine_occupancy(lds, 0));
     int grid = std::min(count, per_cu * c->cus);
     hipError_t e = hac::launch_batch(reinterpret_cast<hac::Instance *>(ws + in_off),
                                      reinterpret_cast<int32_t *>(ws + or_off), count, grid, lds,

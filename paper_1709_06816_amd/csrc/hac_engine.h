@@ -8,7 +8,7 @@
 
 namespace hac {
 
-constexpr int kRunBlock = 1024;      // threads per workgroup of the single-instance kernel
+constexpr int kRunBlock = 1024;      // default threads per workgroup of the single-instance kernel (256, 512 or 1024)
 constexpr int kBatchBlock = 256;     // threads per workgroup of the batch kernel
 constexpr int kSetupBlock = 256;     // threads per workgroup of the set-up kernel
 constexpr int kChunk = 64;           // rows owned in chunks of 64 (one wave's lanes)
@@ -70,7 +70,7 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream);
 // Single instance: set-up kernel over the whole device, then the merge kernel
 // on g workgroups (g > 1 uses a cooperative launch so that all are
 // co-resident).  `setup_done` is recorded on the stream between the two.
-hipError_t launch_run(const Instance &inst, int g, Control *ctl, uint64_t timeout_ticks,
+hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint64_t timeout_ticks,
                       hipStream_t stream, hipEvent_t setup_done);
 
 // `count` instances, one workgroup each, taken in the order of `order`
@@ -83,8 +83,8 @@ hipError_t launch_batch(const Instance *insts, const int32_t *order, int count, 
 // LDS a launch may request.
 hipError_t engine_setup(size_t max_lds, size_t *usable);
 
-// Workgroups of the run (batch = false) or batch kernel that fit on one CU
-// with `lds` bytes of dynamic LDS.
-int engine_occupancy(size_t lds, bool batch);
+// Workgroups of the run kernel with `block` threads (block = 0: the batch
+// kernel) that fit on one CU with `lds` bytes of dynamic LDS.
+int engine_occupancy(size_t lds, int block);
 
 }  // namespace hac

@@ -655,7 +655,8 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I) {
     if (bad) atomicOr(I.status, kErrInput);
 }
 
-__global__ __launch_bounds__(kRunBlock) void k_run(Instance I, Control *ctl, uint64_t timeout) {
+template <int B>
+__global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t timeout) {
     extern __shared__ __align__(16) uint8_t smem[];
     Stats st;
     if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
@@ -665,15 +666,15 @@ __global__ __launch_bounds__(kRunBlock) void k_run(Instance I, Control *ctl, uin
     // The set-up kernel has finished: its status word is final and the same
     // for every thread of every workgroup.
     if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
-    init_masks<kRunBlock>(L, n);
+    init_masks<B>(L, n);
     const int own_ch = own_chunks(n, g, w);
-    for (int li = threadIdx.x; li < own_cap; li += kRunBlock) {
+    for (int li = threadIdx.x; li < own_cap; li += B) {
         const int k = row_of_local(li, g, w);
         L.cache[li] = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmptyRow;
     }
     __syncthreads();
-    merge_loop<kRunBlock>(I, g, w, L, ctl, timeout, st);
-    flush_stats<kRunBlock>(ctl, st);
+    merge_loop<B>(I, g, w, L, ctl, timeout, st);
+    flush_stats<B>(ctl, st);
 }
 
 __global__ __launch_bounds__(kBatchBlock) void k_batch(const Instance *__restrict__ insts,
@@ -735,7 +736,8 @@ size_t lds_bytes(int n, int own, bool in_kernel_setup) {
 hipError_t engine_setup(size_t max_lds, size_t *usable) {
     // Dynamic LDS may use what the static LDS of the kernels leaves free.
     size_t static_max = 0;
-    const void *fns[] = {reinterpret_cast<const void *>(&k_run), reinterpret_cast<const void *>(&k_batch)};
+    const void *fns[] = {reinterpret_cast<const void *>(&k_run<256>), reinterpret_cast<const void *>(&k_run<512>),
+                         reinterpret_cast<const void *>(&k_run<1024>), reinterpret_cast<const void *>(&k_batch)};
     for (const void *fn : fns) {
         hipFuncAttributes a;
         hipError_t e = hipFuncGetAttributes(&a, fn);
@@ -751,10 +753,18 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
     return hipSuccess;
 }
 
-int engine_occupancy(size_t lds, bool batch) {
+static const void *run_kernel(int block) {
+    switch (block) {
+    case 256: return reinterpret_cast<const void *>(&k_run<256>);
+    case 512: return reinterpret_cast<const void *>(&k_run<512>);
+    default: return reinterpret_cast<const void *>(&k_run<1024>);
+    }
+}
+
+int engine_occupancy(size_t lds, int block) {
     int blocks = 0;
-    const void *fn = batch ? reinterpret_cast<const void *>(&k_batch) : reinterpret_cast<const void *>(&k_run);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, batch ? kBatchBlock : kRunBlock, lds) !=
+    const void *fn = block == 0 ? reinterpret_cast<const void *>(&k_batch) : run_kernel(block);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, block == 0 ? kBatchBlock : block, lds) !=
         hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -770,7 +780,7 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_run(const Instance &inst, int g, Control *ctl, uint64_t timeout_ticks,
+hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint64_t timeout_ticks,
                       hipStream_t stream, hipEvent_t setup_done) {
     const int T = (inst.n + 63) / 64;
     hipLaunchKernelGGL(k_setup, dim3((T + 1) / 2), dim3(kSetupBlock), 0, stream, inst);
@@ -781,16 +791,12 @@ hipError_t launch_run(const Instance &inst, int g, Control *ctl, uint64_t timeou
         if (e != hipSuccess) return e;
     }
     const size_t lds = lds_bytes(inst.n, own_rows(inst.n, g), false);
-    if (g == 1) {
-        hipLaunchKernelGGL(k_run, dim3(1), dim3(kRunBlock), lds, stream, inst, ctl, timeout_ticks);
-        return hipGetLastError();
-    }
     Instance a0 = inst;
     Control *a1 = ctl;
     uint64_t a2 = timeout_ticks;
     void *args[] = {&a0, &a1, &a2};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_run), dim3(g), dim3(kRunBlock),
-                                      args, (unsigned)lds, stream);
+    if (g == 1) return hipLaunchKernel(run_kernel(block), dim3(1), dim3(block), args, lds, stream);
+    return hipLaunchCooperativeKernel(run_kernel(block), dim3(g), dim3(block), args, (unsigned)lds, stream);
 }
 
 hipError_t launch_batch(const Instance *insts, const int32_t *order, int count, int grid,
