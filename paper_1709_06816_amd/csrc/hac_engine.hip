@@ -54,7 +54,7 @@ constexpr int kMaxWaves = 16;
 // Loads in flight per thread: chunks per wave per update batch, and 16-byte
 // loads per rescan step.  Large workgroups need fewer per thread for the same
 // bytes in flight and have only 128 VGPRs per thread.
-template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
+template <int B> constexpr int upd_batch() { return B >= 1024 ? 4 : 8; }
 template <int B> constexpr int seg_unroll() { return 8; }
 
 // Order-preserving map of fp32 onto u32 (zeros are canonical +0 here).
@@ -100,29 +100,35 @@ __device__ __forceinline__ uint64_t wave_min(uint64_t v) { return __ockl_wfred_m
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) { return __ockl_wfred_add_u64(v); }
 
-// 64-bit value of the lane picked by DPP control CTRL (all lanes active).
-template <int CTRL>
+// 64-bit value of the lane picked by DPP control CTRL; lanes of rows outside
+// ROW_MASK keep their own value.  All lanes must be active.
+template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const int plo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
+    const int phi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
+    return ((uint64_t)(uint32_t)phi << 32) | (uint32_t)plo;
 }
 
-// Minimum over each group of four lanes (quad_perm [1,0,3,2] then [2,3,0,1]).
-__device__ __forceinline__ uint64_t quad_min(uint64_t v) {
-    v = umin64(v, dpp_u64<0xB1>(v));
-    return umin64(v, dpp_u64<0x4E>(v));
+// Minimum over the wave, valid in lane 63: within quads (quad_perm xor 1,
+// xor 2), half rows (row_half_mirror), rows (row_mirror), then across rows
+// (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
+__device__ __forceinline__ uint64_t wave_min_last(uint64_t v) {
+    v = umin64(v, dpp_u64<0xB1, 0xF>(v));
+    v = umin64(v, dpp_u64<0x4E, 0xF>(v));
+    v = umin64(v, dpp_u64<0x141, 0xF>(v));
+    v = umin64(v, dpp_u64<0x140, 0xF>(v));
+    v = umin64(v, dpp_u64<0x142, 0xA>(v));
+    return umin64(v, dpp_u64<0x143, 0xC>(v));
 }
 
-// Fold every lane's v into the LDS word *acc: a quad reduction, then one
-// atomic minimum per group of four lanes.  Call with every lane of the wave
-// active.
+// Fold every lane's v into the LDS word *acc with one atomic minimum per
+// wave.  Call with every lane of the wave active.
 __device__ __forceinline__ void lds_min(uint64_t *acc, uint64_t v) {
-    v = quad_min(v);
-    if ((threadIdx.x & 3) == 0 && v != ~0ull)
+    v = wave_min_last(v);
+    if ((threadIdx.x & 63) == 63 && v != ~0ull)
         atomicMin(reinterpret_cast<unsigned long long *>(acc), (unsigned long long)v);
 }
-
 
 __device__ __forceinline__ bool is_live(const uint32_t *amask, int l) {
     return (amask[l >> 5] >> (l & 31)) & 1u;
@@ -600,6 +606,11 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         // Cluster i grows; every thread has read size1[i] and size1[j] for
         // this merge, and nothing reads them again before the next one.
         if (tid == 0) L.size1[i] = (uint16_t)(ni + nj - 1);
+        // Start writing this merge's row and column back for the other
+        // workgroups now, so that the release before the next exchange finds
+        // little left to do (the last wave, which starts no rescan segment
+        // first).
+        if (g > 1 && tid == B - 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (prof) st.lap(kPhUpdate);
 
         // ---- refresh rows whose cached partner is gone --------------------
