@@ -54,8 +54,8 @@ constexpr int kMaxWaves = 16;
 // Loads in flight per thread: chunks per wave per update batch, and 16-byte
 // loads per rescan step.  Large workgroups need fewer per thread for the same
 // bytes in flight and have only 128 VGPRs per thread.
-template <int B> constexpr int upd_batch() { return B >= 1024 ? 4 : 8; }
-template <int B> constexpr int seg_unroll() { return 8; }
+template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
+template <int B> constexpr int seg_unroll() { return B >= 1024 ? 4 : 8; }
 
 // Order-preserving map of fp32 onto u32 (zeros are canonical +0 here).
 __device__ __forceinline__ uint32_t ord32(float x) {
@@ -381,14 +381,14 @@ __device__ void init_masks(const Lds &L, int n) {
     for (int k = threadIdx.x; k < n; k += B) L.size1[k] = 0;
 }
 
-// Recompute the cache entries of the rows queued in rlist (their entries were
-// set to kEmptyRow when queued): each becomes the smallest (D[k][l], l) over
-// live l > k.  Row tails are cut into segments of one wave's loads; the waves
+// Rescan the rows queued in rlist (their entries were reset to kEmptyRow when
+// queued): each entry becomes the smallest (D[k][l], l) over live l > k with
+// l != skip.  Row tails are cut into segments of one wave's loads; the waves
 // take segments round-robin across all queued rows and fold their lanes'
 // minima into the entry with LDS atomics, so no barrier is needed per row.
 template <int B>
 __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, const Lds &L,
-                            uint32_t nresc, unsigned long long &elems) {
+                            uint32_t nresc, int skip, unsigned long long &elems) {
     constexpr int W = B / 64, U = seg_unroll<B>();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int base = 0;
@@ -418,6 +418,7 @@ __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, co
                     uint32_t m = (L.amask[q >> 3] >> ((q & 7) * 4)) & 0xFu;  // live l = 4q..4q+3
                     const int below = k + 1 - 4 * q;                           // those with l <= k
                     if (below > 0) m &= (0xFu << below) & 0xFu;
+                    if ((skip >> 2) == q) m &= ~(1u << (skip & 3));
                     elems += __popc(m);
                     const float v[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
 #pragma unroll
@@ -441,7 +442,7 @@ __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, co
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int l = l0 + sg * 64 * U + u * 64 + lane;
-                    if (l < n && is_live(L.amask, l)) {
+                    if (l < n && l != skip && is_live(L.amask, l)) {
                         best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
                         ++elems;
                     }
@@ -470,11 +471,24 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // All n-1 merges of one instance on workgroup w of a group of g.  On entry
 // the cache holds every owned row's first minimum, the masks are initialised
 // and the input is known to be valid.
+//
+// Cache maintenance after merging (i, j), for an owned live row k:
+//   * k < i: the row gains the entry (v_k, i) and loses column j.  If its
+//     partner was i or j, the new minimum is min(minimum over l != i, j,
+//     (v_k, i)); otherwise min(old entry, (v_k, i)).
+//   * i < k < j: the row loses column j; if its partner was j its minimum is
+//     recomputed over l != j (column i lies to its left).
+//   * k > j: unchanged.
+// Rows whose partner was i or j are therefore rescanned over l not in {i, j}
+// right after the argmin, overlapping the loads of rows i and j, and the new
+// (v_k, i) is folded in afterwards with an atomic minimum.  Ties resolve as
+// in the lexicographic order: any other column attaining the old minimum lies
+// to the right of the old partner.
 template <int B>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
                            uint64_t timeout, Stats &st) {
     constexpr int W = B / 64;
-    constexpr int kUpdBatch = upd_batch<B>();
+    constexpr int U = upd_batch<B>();
     const int n = I.n, link = I.link;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
     const int own_ch = own_chunks(n, g, w);
@@ -509,7 +523,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         }
         if (prof) st.lap(s == 0 ? kPhSetup : kPhWait);
         // Row i_prev's new cache entry: its smallest new value to the right.
-        // The thread that owns it in the update below stores it.
         const uint64_t ip_entry = ((uint32_t)(p2 >> 32) != kEmptyOrd) ? p2 : kEmptyRow;
         uint64_t key_ip = kEmpty;
         if (i_prev >= 0 && (uint32_t)(p2 >> 32) != kEmptyOrd)
@@ -537,12 +550,42 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             reinterpret_cast<int4 *>(I.out)[s] = rec;
         }
         if (s == n - 2) break;
-        // Slot j is retired (Section 5.3 step 6).  Other threads test other
-        // bits of the same mask word meanwhile, hence the atomic.
+
+        // ---- loads of rows i and j for the first batch of owned columns ---
+        float *Di = D + (size_t)i * n;
+        const float *Dj = D + (size_t)j * n;
+        float a[U], bv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int lq = wv + u * W;
+            const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
+            a[u] = k < n ? Di[k] : 0.0f;
+            bv[u] = k < n ? Dj[k] : 0.0f;
+        }
+        // ---- retire j (Section 5.3 step 6); queue rows whose partner is i or j
         if (tid == 0) {
             atomicAnd(&L.amask[j >> 5], ~(1u << (j & 31)));
             if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
         }
+        for (int li = tid; li < own_ch * 64; li += B) {
+            const int k = row_of_local(li, g, w);
+            if (k >= n || k == i || k == j) continue;
+            uint64_t c = L.cache[li];
+            if (k == i_prev) {
+                c = ip_entry;
+                L.cache[li] = c;
+            }
+            const int nn = (int)((c >> 16) & 0xFFFFull);
+            if ((uint32_t)(c >> 32) != kEmptyOrd && (nn == i || nn == j)) {
+                L.cache[li] = kEmptyRow;  // rebuilt by the rescan below
+                L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
+            }
+        }
+        __syncthreads();
+        if (prof) st.lap(kPhUpdate);
+        const uint32_t nresc = s_nresc;
+        if (nresc) rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems);
+        if (prof) st.lap(kPhRescan);
 
         // ---- Lance-Williams update of row/column i (Section 4 step 3) -----
         float ai = 0.0f, aj = 0.0f;
@@ -551,84 +594,49 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             ai = (float)((double)ni / sum);
             aj = (float)((double)nj / sum);
         }
-        float *Di = D + (size_t)i * n;
-        const float *Dj = D + (size_t)j * n;
         uint64_t q2 = kEmpty;
-        for (int lq0 = wv; lq0 < own_ch; lq0 += W * kUpdBatch) {
-            float a[kUpdBatch], bv[kUpdBatch];
+        for (int lq0 = wv; lq0 < own_ch; lq0 += W * U) {
+            if (lq0 != wv) {
 #pragma unroll
-            for (int u = 0; u < kUpdBatch; ++u) {
-                const int lq = lq0 + u * W;
-                const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-                const bool ok = k < n;
-                a[u] = ok ? Di[k] : 0.0f;
-                bv[u] = ok ? Dj[k] : 0.0f;
+                for (int u = 0; u < U; ++u) {
+                    const int lq = lq0 + u * W;
+                    const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
+                    a[u] = k < n ? Di[k] : 0.0f;
+                    bv[u] = k < n ? Dj[k] : 0.0f;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < kUpdBatch; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int lq = lq0 + u * W;
                 if (lq >= own_ch) break;
                 const int k = chunk_of(lq, g, w) * 64 + lane;
                 if (k >= n || k == i || k == j || !is_live(L.amask, k)) continue;
-                const int li = lq * 64 + lane;
-                const uint64_t c = k == i_prev ? ip_entry : L.cache[li];
-                if (k == i_prev) L.cache[li] = ip_entry;
-                const int nk = (int)L.size1[k] + 1;
+                const int nk = link == HAC_WARD ? (int)L.size1[k] + 1 : 1;
                 const float v = lw_update(link, a[u], bv[u], h, ni, nj, nk, ai, aj);
                 Di[k] = v;
                 D[(size_t)k * n + i] = v;
                 st.update_elems++;
-                const uint32_t ov = ord32(v);
-                if (k > i) q2 = umin64(q2, ((uint64_t)ov << 32) | ((uint64_t)k << 16));
-                const int nn = (int)((c >> 16) & 0xFFFFull);
-                bool requeue = false;
-                if (k < i) {
-                    const uint32_t oc = (uint32_t)(c >> 32);
-                    if (nn == i || nn == j) {
-                        if (ov <= oc)
-                            L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16);
-                        else
-                            requeue = true;
-                    } else if (ov < oc || (ov == oc && i < nn)) {
-                        L.cache[li] = ((uint64_t)ov << 32) | ((uint64_t)i << 16);
-                    }
-                } else if (k < j && nn == j) {
-                    requeue = true;
-                }
-                if (requeue) {
-                    L.cache[li] = kEmptyRow;  // rebuilt by the rescan below
-                    L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
-                }
+                const uint64_t key = ((uint64_t)ord32(v) << 32) | ((uint64_t)i << 16);
+                if (k > i) q2 = umin64(q2, ((uint64_t)ord32(v) << 32) | ((uint64_t)k << 16));
+                if (k < i)  // the row's new entry at column i (see above)
+                    atomicMin(reinterpret_cast<unsigned long long *>(&L.cache[(lq * 64) + lane]),
+                              (unsigned long long)key);
             }
         }
         lds_min(&s_acc[b ^ 1][1], q2);  // row i's candidates for epoch e+1
         __syncthreads();
         // Cluster i grows; every thread has read size1[i] and size1[j] for
         // this merge, and nothing reads them again before the next one.
-        if (tid == 0) L.size1[i] = (uint16_t)(ni + nj - 1);
-        // Start writing this merge's row and column back for the other
-        // workgroups now, so that the release before the next exchange finds
-        // little left to do (the last wave, which starts no rescan segment
-        // first).
-        if (g > 1 && tid == B - 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (prof) st.lap(kPhUpdate);
-
-        // ---- refresh rows whose cached partner is gone --------------------
-        const uint32_t nresc = s_nresc;
-        if (nresc) {
-            rescan_rows<B>(D, n, g, w, L, nresc, st.rescan_elems);
-            __syncthreads();
-            if (tid == 0) {
-                st.rescans += nresc;
-                s_nresc = 0;
-            }
+        if (tid == 0) {
+            L.size1[i] = (uint16_t)(ni + nj - 1);
+            st.rescans += nresc;
+            s_nresc = 0;
         }
-        if (prof) st.lap(kPhRescan);
+        if (prof) st.lap(kPhCand);
 
         // ---- local candidates for the next argmin -------------------------
         fold_candidates<B>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
         i_prev = i;
-        if (prof) st.lap(kPhCand);
     }
 }
 
