@@ -16,8 +16,7 @@
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kDefaultSingleWgN = 2048;
-constexpr int kDefaultWorkgroups = 16;
+constexpr int kDefaultSingleWgN = 1536;
 constexpr int64_t kDefaultTimeoutMs = 10000;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -318,7 +317,8 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     const int single_n = c->opt_single_n > 0 ? (int)c->opt_single_n : kDefaultSingleWgN;
     int g = 1;
     if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1), false) > c->lds_max) {
-        int want = c->opt_wgs > 0 ? (int)c->opt_wgs : kDefaultWorkgroups;
+        // Measured on MI355X: about one workgroup per 512 items, up to 64.
+        int want = c->opt_wgs > 0 ? (int)c->opt_wgs : std::max(2, std::min(64, n / 512));
         g = std::max(1, std::min(want, nch));
         while (g < nch && hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max) ++g;
         const size_t lds = hac::lds_bytes(n, hac::own_rows(n, g), false);
