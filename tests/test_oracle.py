@@ -296,3 +296,24 @@ def test_thread_count_invariance():
     a = oracle.run_f32(d, "ward", threads=1)
     b = oracle.run_f32(d, "ward", threads=7)
     assert a.tobytes() == b.tobytes()
+
+
+@pytest.mark.parametrize("link", LINKS)
+def test_replay_reproduces_fp64_oracle(link):
+    """The fp64 replay checker, fed the fp64 oracle's own merge list, must
+    return exactly the oracle's heights, and every listed pair must be the
+    fp64 minimum at its step (optimality with no slack)."""
+    d = synth.rmsd_like(seed=8, n=300)
+    m = oracle.run_f64(d.astype(np.float64), link)
+    h64, min64 = oracle.replay_f64(d, link, m, opt_stride=1)
+    assert np.array_equal(h64, m["h"])
+    assert np.array_equal(h64, min64)
+
+
+def test_replay_rejects_invalid_lists():
+    d = synth.uniform_matrix(8, 2)
+    m = oracle.run_f32(d, "single")
+    bad = m.copy()
+    bad[3]["j"] = bad[1]["j"]  # a slot retired twice
+    with pytest.raises(oracle.OracleError):
+        oracle.replay_f64(d, "single", bad)
