@@ -141,6 +141,18 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        (reported in hac_stats.phase_*; adds ~0.5 us per merge)
  *   HAC_OPT_BLOCK        threads per workgroup of hac_run: 256, 512 or 1024
  *                        (0 = automatic)
+ *   HAC_OPT_AUTOTUNE     hac_batch picks its launch plan (threads per workgroup,
+ *                        workgroups per large instance) by timing candidates on a
+ *                        scratch copy of the first batch of each size mix, and
+ *                        caches the choice in the context (1 = on, the default;
+ *                        0 = off).  Costs a few extra runs of that first batch.
+ *   HAC_OPT_BATCH_BLOCK  force hac_batch's threads per workgroup: 256 or 1024
+ *   HAC_OPT_BATCH_GROUP  force hac_batch's workgroups per large instance (1..64)
+ *   HAC_OPT_GRAPH        hac_batch enqueues its descriptor upload, fills and
+ *                        kernel as one HIP graph, instantiated once per layout
+ *                        (instance count, plan, workspace) and relaunched with
+ *                        the new descriptors (1 = on, the default; 0 = plain
+ *                        stream launches).  Results are identical either way.
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
@@ -148,7 +160,11 @@ typedef enum {
     HAC_OPT_TIMEOUT_MS = 3,
     HAC_OPT_EXCHANGE = 4,
     HAC_OPT_PROFILE = 5,
-    HAC_OPT_BLOCK = 6
+    HAC_OPT_BLOCK = 6,
+    HAC_OPT_AUTOTUNE = 7,
+    HAC_OPT_BATCH_BLOCK = 8,
+    HAC_OPT_BATCH_GROUP = 9,
+    HAC_OPT_GRAPH = 10
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 
@@ -160,12 +176,18 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *   rescan_elems:      matrix entries read by those recomputations
  *   update_elems:      (k) entries updated by the Lance-Williams step, summed over merges
  *   workgroups:        workgroups the merge kernel ran with
+ *   block:             threads per workgroup
  *   phase_avg_ms[5]:   time per workgroup (device wall clock), averaged over the
  *                      workgroups, spent in: [0] set-up (mirror, checks, first
  *                      row minima), [1] waiting for / combining the group's
  *                      partial minima, [2] the Lance-Williams update, [3] row
  *                      rescans, [4] local candidate reduction
  *   phase_max_ms[5]:   the same, largest workgroup
+ *   group:             hac_run: workgroups on the instance (= workgroups);
+ *                      hac_batch: workgroups per large instance in the plan used
+ *   graph:             hac_batch: 0 = stream launches, 1 = an existing graph was
+ *                      relaunched, 2 = a graph was built for this call; with a
+ *                      graph kernel_ms covers upload, fills and kernel
  */
 typedef struct {
     double kernel_ms;
@@ -174,9 +196,11 @@ typedef struct {
     int64_t rescan_elems;
     int64_t update_elems;
     int32_t workgroups;
-    int32_t reserved;
+    int32_t block;
     double phase_avg_ms[5];
     double phase_max_ms[5];
+    int32_t group;
+    int32_t graph;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

@@ -34,6 +34,7 @@ HAC_OK, HAC_EINVAL, HAC_EINPUT, HAC_ENOMEM, HAC_EDEVICE, HAC_ENODEV, HAC_EBUSY, 
 PRESERVE_INPUT = 1
 OUT_DEVICE = 2
 OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE, OPT_PROFILE, OPT_BLOCK = 1, 2, 3, 4, 5, 6
+OPT_AUTOTUNE, OPT_BATCH_BLOCK, OPT_BATCH_GROUP, OPT_GRAPH = 7, 8, 9, 10
 MAX_N = 65536
 MAX_BATCH_N = 8192
 
@@ -59,8 +60,9 @@ class _Stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("init_ms", ctypes.c_double),
                 ("rescans", ctypes.c_int64), ("rescan_elems", ctypes.c_int64),
                 ("update_elems", ctypes.c_int64), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("phase_avg_ms", ctypes.c_double * 5),
-                ("phase_max_ms", ctypes.c_double * 5)]
+                ("block", ctypes.c_int32), ("phase_avg_ms", ctypes.c_double * 5),
+                ("phase_max_ms", ctypes.c_double * 5), ("group", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")

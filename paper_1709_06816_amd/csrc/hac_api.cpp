@@ -8,6 +8,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "hac.h"
@@ -20,6 +21,12 @@ constexpr int kDefaultSingleWgN = 1536;
 constexpr int64_t kDefaultTimeoutMs = 10000;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// How one hac_batch call is laid out on the device.
+struct BatchPlan {
+    int block = 256;  // threads per workgroup
+    int group = 1;    // workgroups per large instance (1 = every instance on one workgroup)
+};
 
 }  // namespace
 
@@ -44,13 +51,16 @@ struct hac_ctx {
 
     hac_stats stats{};
     int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0, opt_exchange = 0, opt_profile = 0;
-    int64_t opt_block = 0;
+    int64_t opt_block = 0, opt_batch_block = 0, opt_batch_group = 0, opt_autotune = 1;
+    std::unordered_map<std::string, BatchPlan> plans;  // tuned batch plans by size mix
+    int64_t opt_graph = 1;
+    std::unordered_map<std::string, hipGraphExec_t> graphs;  // batch graphs by layout
 
     // State of the last enqueued call, for hac_sync / stats.
     bool pending = false;
     hipStream_t pending_stream = nullptr;
     int pending_count = 0;           // status words to check
-    int pending_wgs = 0;
+    int pending_wgs = 0, pending_block = 0, pending_group = 0, pending_graph = 0;
 };
 
 namespace {
@@ -128,6 +138,13 @@ int set_device(hac_ctx *c) {
     return HAC_OK;
 }
 
+void clear_graphs(hac_ctx *c) {
+    if (c->graphs.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
 uint64_t timeout_ticks(const hac_ctx *c) {
     int64_t ms = c->opt_timeout_ms > 0 ? c->opt_timeout_ms : kDefaultTimeoutMs;
     return (uint64_t)ms * (uint64_t)(c->wallclock_khz > 0 ? c->wallclock_khz : 100000);
@@ -135,7 +152,7 @@ uint64_t timeout_ticks(const hac_ctx *c) {
 
 // Workgroups that can be co-resident for a hac_run launch with `lds` bytes.
 int max_coresident(hac_ctx *c, size_t lds, int block) {
-    int per_cu = hac::engine_occupancy(lds, block);
+    int per_cu = hac::engine_occupancy(lds, block, false);
     if (per_cu < 1) per_cu = 1;
     return per_cu * c->cus;
 }
@@ -154,6 +171,9 @@ int check_status(hac_ctx *c) {
     c->stats.rescan_elems = (int64_t)ctl->rescan_elems;
     c->stats.update_elems = (int64_t)ctl->update_elems;
     c->stats.workgroups = c->pending_wgs;
+    c->stats.block = c->pending_block;
+    c->stats.group = c->pending_group;
+    c->stats.graph = c->pending_graph;
     const double khz = c->wallclock_khz > 0 ? c->wallclock_khz : 100000.0;
     for (int p = 0; p < 5; ++p) {
         c->stats.phase_avg_ms[p] = (double)ctl->prof_sum[p] / khz / std::max(1, c->pending_wgs);
@@ -188,6 +208,184 @@ int finish(hac_ctx *c, hipStream_t s, int nstatus, hac_merge *out, size_t nrec, 
     int rc = check_status(c);
     if (rc != HAC_OK) return rc;
     if (nrec) HIP_TRY(c, hipMemcpy(out, c->dout, nrec * sizeof(hac_merge), hipMemcpyDeviceToHost));
+    return HAC_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Instances at least this large may get a group of workgroups.
+constexpr int kGroupMinN = 2048;
+
+// Signature of a batch for the plan cache: size histogram (powers of two) and
+// linkage mix.
+std::string batch_signature(const int32_t *ns, const int32_t *links, int count) {
+    int hist[18] = {0}, lk[4] = {0};
+    for (int k = 0; k < count; ++k) {
+        int b = 0;
+        while ((1 << (b + 1)) <= ns[k] && b < 17) ++b;
+        hist[b]++;
+        lk[links[k] & 3]++;
+    }
+    std::string s = std::to_string(count);
+    for (int b = 0; b < 18; ++b) s += "," + std::to_string(hist[b]);
+    for (int q = 0; q < 4; ++q) s += ";" + std::to_string(lk[q]);
+    return s;
+}
+
+// Where one batch call's pieces sit in the workspace.
+struct BatchLayout {
+    hac::BatchLaunch L{};
+    size_t st_off = 0, st_bytes = 0;   // control block + statuses: [0, st_off + st_bytes)
+    size_t in_off = 0, up_bytes = 0;   // descriptors, order, groups: uploaded as one block
+    size_t sl_off = 0, sl_bytes = 0;   // exchange slots of the groups
+    int group = 1;
+};
+
+// Lay out a batch for `plan`, write its descriptors into the pinned staging
+// buffer and fill `B`.  The caller has validated the batch.  Nothing is
+// enqueued.
+int batch_prepare(hac_ctx *c, float *base, const int64_t *offsets, const int32_t *ns,
+                  const int32_t *links, int count, hac_merge *dev_out, const int64_t *out_offsets,
+                  const BatchPlan &plan, hipStream_t s, BatchLayout *B) {
+    std::vector<int32_t> ord(count);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return ns[a] > ns[b]; });
+
+    // Groups for the largest instances, on workgroups 0, g, 2g, ... while at
+    // most half of the co-resident workgroups are taken.
+    const size_t lds1 = hac::lds_bytes(ns[ord[0]], hac::own_rows(ns[ord[0]], 1), true);
+    int per_cu = std::max(1, hac::engine_occupancy(lds1, plan.block, true));
+    int cap = per_cu * c->cus;
+    std::vector<int32_t> gbase, gsize;
+    int used = 0;
+    if (plan.group > 1) {
+        for (int t = 0; t < count; ++t) {
+            const int n = ns[ord[t]];
+            if (n < kGroupMinN || used + plan.group > cap / 2) break;
+            gbase.push_back(used);
+            gsize.push_back(plan.group);
+            used += plan.group;
+        }
+    }
+    const int ngroups = (int)gbase.size();
+    size_t lds = 0;
+    for (int t = 0; t < count; ++t) {
+        const int n = ns[ord[t]], g = t < ngroups ? plan.group : 1;
+        lds = std::max(lds, hac::lds_bytes(n, hac::own_rows(n, g), true));
+        if (lds > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit one workgroup's LDS", n);
+        if (t >= ngroups) break;  // the rest are no larger than this one
+    }
+    per_cu = std::max(1, hac::engine_occupancy(lds, plan.block, true));
+    cap = per_cu * c->cus;
+    const int grid = std::max(used, std::min(cap, used + (count - ngroups)));
+    if (grid > cap) return fail(c, HAC_EINVAL, "batch plan needs %d co-resident workgroups", grid);
+
+    const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
+    const size_t st_off = ctl_bytes, st_bytes = align_up((size_t)count * 4, kAlign);
+    const size_t in_off = st_off + st_bytes, in_bytes = align_up((size_t)count * sizeof(hac::Instance), kAlign);
+    const size_t or_off = in_off + in_bytes, or_bytes = align_up((size_t)count * 4, kAlign);
+    const size_t gb_off = or_off + or_bytes, gb_bytes = align_up((size_t)std::max(ngroups, 1) * 8, kAlign);
+    const size_t sl_off = gb_off + gb_bytes;
+    const size_t sl_each = (size_t)2 * (plan.group + 1) * hac::kSlotStride * 8;
+    const size_t sl_bytes = (size_t)ngroups * sl_each;
+    int rc = ensure_dev(c, &c->ws, &c->ws_cap, sl_off + sl_bytes, "workspace");
+    if (rc) return rc;
+    const size_t up_bytes = in_bytes + or_bytes + gb_bytes;
+    rc = ensure_pinned(c, std::max(ctl_bytes + st_bytes, up_bytes));
+    if (rc) return rc;
+    char *ws = reinterpret_cast<char *>(c->ws);
+    // The pinned buffer may still be the source or target of an earlier copy.
+    HIP_TRY(c, hipStreamSynchronize(s));
+    char *pin = reinterpret_cast<char *>(c->pinned);
+    hac::Instance *hin = reinterpret_cast<hac::Instance *>(pin);
+    for (int k = 0; k < count; ++k) {
+        hac::Instance &I = hin[k];
+        I.D = base + offsets[k];
+        I.out = dev_out + out_offsets[k];
+        I.rowkey = nullptr;
+        I.slots = nullptr;
+        I.status = reinterpret_cast<uint32_t *>(ws + st_off) + k;
+        I.n = ns[k];
+        I.link = links[k];
+        I.exchange = 0;
+        I.flags = c->opt_profile ? hac::kFlagProfile : 0;
+    }
+    for (int t = 0; t < ngroups; ++t)
+        hin[ord[t]].slots = reinterpret_cast<uint64_t *>(ws + sl_off + (size_t)t * sl_each);
+    std::memcpy(pin + in_bytes, ord.data(), (size_t)count * 4);
+    int32_t *hg = reinterpret_cast<int32_t *>(pin + in_bytes + or_bytes);
+    for (int t = 0; t < ngroups; ++t) {
+        hg[t] = gbase[t];
+        hg[ngroups + t] = gsize[t];
+    }
+
+    hac::BatchLaunch &L = B->L;
+    L.insts = reinterpret_cast<hac::Instance *>(ws + in_off);
+    L.order = reinterpret_cast<int32_t *>(ws + or_off);
+    L.count = count;
+    L.gbase = reinterpret_cast<int32_t *>(ws + gb_off);
+    L.gsize = reinterpret_cast<int32_t *>(ws + gb_off) + ngroups;
+    L.ngroups = ngroups;
+    L.block = plan.block;
+    L.grid = grid;
+    L.lds = lds;
+    B->st_off = st_off;
+    B->st_bytes = st_bytes;
+    B->in_off = in_off;
+    B->up_bytes = up_bytes;
+    B->sl_off = sl_off;
+    B->sl_bytes = sl_bytes;
+    B->group = ngroups ? plan.group : 1;
+    return HAC_OK;
+}
+
+// Enqueue a prepared batch: descriptor upload, zero fills, then (after
+// `before_kernel`, if given, is recorded) the kernel.
+hipError_t batch_enqueue(hac_ctx *c, const BatchLayout &B, hipStream_t s, hipEvent_t before_kernel) {
+    char *ws = reinterpret_cast<char *>(c->ws);
+    hipError_t e = hipMemcpyAsync(ws + B.in_off, c->pinned, B.up_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hac::launch_zero(ws, (B.st_off + B.st_bytes) / 4, s);
+    if (e == hipSuccess && B.sl_bytes) e = hac::launch_zero(ws + B.sl_off, B.sl_bytes / 4, s);
+    if (e == hipSuccess && before_kernel) e = hipEventRecord(before_kernel, s);
+    if (e == hipSuccess) e = hac::launch_batch(B.L, reinterpret_cast<hac::Control *>(ws), timeout_ticks(c), s);
+    return e;
+}
+
+// Time each candidate plan once on a scratch copy of the batch and return
+// the fastest; results never depend on the plan.
+int batch_autotune(hac_ctx *c, float *packed, int64_t extent, const int64_t *offsets,
+                   const int32_t *ns, const int32_t *links, int count, hac_merge *dev_out,
+                   const int64_t *out_offsets, hipStream_t s, BatchPlan *best) {
+    const BatchPlan cands[] = {{256, 1}, {1024, 1}, {256, 4}, {256, 8}, {1024, 4}, {1024, 8}};
+    float *scratch = nullptr;
+    size_t scratch_cap = 0;
+    int rc = ensure_dev(c, reinterpret_cast<void **>(&scratch), &scratch_cap, (size_t)extent * 4, "tuning copy");
+    if (rc) return rc;
+    float best_ms = 1e30f;
+    *best = cands[0];
+    for (const BatchPlan &p : cands) {
+        hipError_t e = hipMemcpyAsync(scratch, packed, (size_t)extent * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) break;
+        BatchLayout B;
+        if (batch_prepare(c, scratch, offsets, ns, links, count, dev_out, out_offsets, p, s, &B) != HAC_OK)
+            continue;
+        e = batch_enqueue(c, B, s, c->ev[1]);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        if (hipEventRecord(c->ev[2], s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) break;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            *best = p;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(scratch);
+    c->err.clear();
     return HAC_OK;
 }
 
@@ -240,6 +438,7 @@ int hac_destroy(hac_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->own) (void)hipStreamSynchronize(c->own);
     (void)hipDeviceSynchronize();
+    clear_graphs(c);
     if (c->ws) (void)hipFree(c->ws);
     if (c->dcopy) (void)hipFree(c->dcopy);
     if (c->dout) (void)hipFree(c->dout);
@@ -261,6 +460,17 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
     case HAC_OPT_SINGLE_WG_N: c->opt_single_n = value; return HAC_OK;
     case HAC_OPT_TIMEOUT_MS: c->opt_timeout_ms = value; return HAC_OK;
     case HAC_OPT_PROFILE: c->opt_profile = value != 0; return HAC_OK;
+    case HAC_OPT_BATCH_BLOCK:
+        if (value != 0 && value != 256 && value != 1024)
+            return fail(c, HAC_EINVAL, "batch block size %lld is not 256 or 1024", (long long)value);
+        c->opt_batch_block = value;
+        return HAC_OK;
+    case HAC_OPT_BATCH_GROUP:
+        if (value > 64) return fail(c, HAC_EINVAL, "batch group %lld > 64", (long long)value);
+        c->opt_batch_group = value;
+        return HAC_OK;
+    case HAC_OPT_AUTOTUNE: c->opt_autotune = value != 0; return HAC_OK;
+    case HAC_OPT_GRAPH: c->opt_graph = value != 0; return HAC_OK;
     case HAC_OPT_BLOCK:
         if (value != 0 && value != 256 && value != 512 && value != 1024)
             return fail(c, HAC_EINVAL, "block size %lld is not 256, 512 or 1024", (long long)value);
@@ -378,6 +588,8 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     if (e != hipSuccess) return hip_fail(c, e, "merge kernel launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     c->pending_wgs = g;
+    c->pending_block = block;
+    c->pending_group = g;
     return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags);
 }
 
@@ -392,7 +604,6 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         return fail(c, HAC_EINVAL, "NULL argument");
     if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
     int64_t extent = 0, rec_extent = 0;
-    int nmax = 1;
     for (int k = 0; k < count; ++k) {
         if (ns[k] < 1 || ns[k] > HAC_MAX_BATCH_N)
             return fail(c, HAC_EINVAL, "instance %d: n=%d outside 1..%d", k, ns[k], HAC_MAX_BATCH_N);
@@ -400,24 +611,12 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         if (offsets[k] < 0 || out_offsets[k] < 0) return fail(c, HAC_EINVAL, "instance %d: negative offset", k);
         extent = std::max(extent, offsets[k] + (int64_t)ns[k] * ns[k]);
         rec_extent = std::max(rec_extent, out_offsets[k] + (int64_t)ns[k] - 1);
-        nmax = std::max(nmax, (int)ns[k]);
     }
-    const size_t lds = hac::lds_bytes(nmax, hac::own_rows(nmax, 1), true);
-    if (lds > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit one workgroup's LDS", nmax);
     int rc = set_device(c);
     if (rc) return rc;
     if (c->pending) (void)hac_sync(c);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     c->stats = hac_stats{};
-
-    const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
-    const size_t st_off = ctl_bytes, st_bytes = align_up((size_t)count * 4, kAlign);
-    const size_t in_off = st_off + st_bytes, in_bytes = align_up((size_t)count * sizeof(hac::Instance), kAlign);
-    const size_t or_off = in_off + in_bytes, or_bytes = align_up((size_t)count * 4, kAlign);
-    rc = ensure_dev(c, &c->ws, &c->ws_cap, or_off + or_bytes, "workspace");
-    if (rc) return rc;
-    rc = ensure_pinned(c, std::max(ctl_bytes + st_bytes, in_bytes + or_bytes));
-    if (rc) return rc;
 
     float *base = packed;
     if (flags & HAC_PRESERVE_INPUT) {
@@ -437,43 +636,60 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         dev_out = c->dout;
     }
 
-    // Descriptors, and the longest-processing-time-first order (largest n first).
-    char *ws = reinterpret_cast<char *>(c->ws);
-    // The pinned buffer is reused below for the read-back; make sure no
-    // earlier copy out of it is still pending.
-    HIP_TRY(c, hipStreamSynchronize(s));
-    hac::Instance *hin = reinterpret_cast<hac::Instance *>(c->pinned);
-    int32_t *hord = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(c->pinned) + in_bytes);
-    for (int k = 0; k < count; ++k) {
-        hac::Instance &I = hin[k];
-        I.D = base + offsets[k];
-        I.out = dev_out + out_offsets[k];
-        I.rowkey = nullptr;
-        I.slots = nullptr;
-        I.status = reinterpret_cast<uint32_t *>(ws + st_off) + k;
-        I.n = ns[k];
-        I.link = linkages[k];
-        I.exchange = 0;
-        I.flags = c->opt_profile ? hac::kFlagProfile : 0;
+    // Plan: forced by options, cached for this size mix, or tuned now.
+    BatchPlan plan;
+    if (c->opt_batch_block > 0 || c->opt_batch_group > 0) {
+        if (c->opt_batch_block > 0) plan.block = (int)c->opt_batch_block;
+        if (c->opt_batch_group > 0) plan.group = (int)c->opt_batch_group;
+    } else {
+        const std::string sig = batch_signature(ns, linkages, count);
+        auto it = c->plans.find(sig);
+        if (it != c->plans.end()) {
+            plan = it->second;
+        } else if (c->opt_autotune && count >= 8) {
+            rc = batch_autotune(c, base, extent, offsets, ns, linkages, count, dev_out, out_offsets, s, &plan);
+            if (rc) return rc;
+            c->plans[sig] = plan;
+        }
     }
-    std::vector<int32_t> ord(count);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return ns[a] > ns[b]; });
-    std::memcpy(hord, ord.data(), (size_t)count * 4);
-    HIP_TRY(c, hipMemcpyAsync(ws + in_off, c->pinned, in_bytes + or_bytes, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
 
+    BatchLayout B;
+    rc = batch_prepare(c, base, offsets, ns, linkages, count, dev_out, out_offsets, plan, s, &B);
+    if (rc) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
-    HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
-    HIP_TRY(c, hipEventRecord(c->ev[1], s));
-    int per_cu = std::max(1, hac::engine_occupancy(lds, 0));
-    int grid = std::min(count, per_cu * c->cus);
-    hipError_t e = hac::launch_batch(reinterpret_cast<hac::Instance *>(ws + in_off),
-                                     reinterpret_cast<int32_t *>(ws + or_off), count, grid, lds,
-                                     reinterpret_cast<hac::Control *>(ws), timeout_ticks(c), s);
-    if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
+    int graphed = 0;
+    if (c->opt_graph) {
+        HIP_TRY(c, hipEventRecord(c->ev[1], s));
+        // One executable graph per layout; descriptors are re-read from the
+        // pinned buffer at every launch.
+        char key[256];
+        snprintf(key, sizeof key, "%p:%zu:%zu:%zu:%zu:%d:%d:%d:%d:%zu:%llu", c->ws, B.in_off, B.up_bytes, B.st_off + B.st_bytes,
+                 B.sl_bytes, B.L.count, B.L.ngroups, B.L.block, B.L.grid, B.L.lds,
+                 (unsigned long long)timeout_ticks(c));
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            if (c->graphs.size() >= 16) clear_graphs(c);
+            char *ws = reinterpret_cast<char *>(c->ws);
+            hipGraphExec_t ex = nullptr;
+            hipError_t ge = hac::build_batch_graph(B.L, reinterpret_cast<hac::Control *>(ws), timeout_ticks(c),
+                                                   ws + B.in_off, c->pinned, B.up_bytes, ws,
+                                                   (B.st_off + B.st_bytes) / 4, ws + B.sl_off, B.sl_bytes / 4, &ex);
+            if (ge != hipSuccess) return hip_fail(c, ge, "building the batch graph");
+            it = c->graphs.emplace(key, ex).first;
+            graphed = 2;
+        } else {
+            graphed = 1;
+        }
+        HIP_TRY(c, hipGraphLaunch(it->second, s));
+    } else {
+        hipError_t e = batch_enqueue(c, B, s, c->ev[1]);
+        if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
+    }
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
-    c->pending_wgs = grid;
+    c->pending_wgs = B.L.grid;
+    c->pending_block = plan.block;
+    c->pending_group = B.group;
+    c->pending_graph = graphed;
     return finish(c, s, count, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)rec_extent, flags);
 }
 

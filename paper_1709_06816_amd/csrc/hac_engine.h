@@ -9,7 +9,7 @@
 namespace hac {
 
 constexpr int kRunBlock = 1024;      // default threads per workgroup of the single-instance kernel (256, 512 or 1024)
-constexpr int kBatchBlock = 256;     // threads per workgroup of the batch kernel
+constexpr int kBatchBlock = 256;     // default threads per workgroup of the batch kernel (256 or 1024)
 constexpr int kSetupBlock = 256;     // threads per workgroup of the set-up kernel
 constexpr int kChunk = 64;           // rows owned in chunks of 64 (one wave's lanes)
 constexpr int kTile = 64;            // mirror tile edge
@@ -73,18 +73,40 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream);
 hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint64_t timeout_ticks,
                       hipStream_t stream, hipEvent_t setup_done);
 
-// `count` instances, one workgroup each, taken in the order of `order`
-// (device int32[count]) from a queue; grid workgroups.
-hipError_t launch_batch(const Instance *insts, const int32_t *order, int count, int grid,
-                        size_t lds, Control *ctl, uint64_t timeout_ticks, hipStream_t stream);
+// A batch launch: `count` instances in the order of `order` (device
+// int32[count], largest first); the first `ngroups` of them run on fixed
+// groups of workgroups (device int32 gbase/gsize[ngroups]), the rest one
+// workgroup each from a queue.
+struct BatchLaunch {
+    const Instance *insts;
+    const int32_t *order;
+    int count;
+    const int32_t *gbase;
+    const int32_t *gsize;
+    int ngroups;
+    int block;   // 256 or 1024 threads per workgroup
+    int grid;    // workgroups (all co-resident)
+    size_t lds;  // dynamic LDS per workgroup
+};
+hipError_t launch_batch(const BatchLaunch &b, Control *ctl, uint64_t timeout_ticks, hipStream_t stream);
+
+// An executable graph of one batch call: copy `up_bytes` from pinned host
+// memory `up_src` to `up_dst`, zero `z0_words` u32 at z0 and `z1_words` at z1
+// with fill kernels (no memset nodes), then the batch kernel, marked
+// cooperative when it has groups.  The graph reads the descriptors from
+// `up_src` at every launch, so new descriptors of the same shape need no
+// rebuild.
+hipError_t build_batch_graph(const BatchLaunch &b, Control *ctl, uint64_t timeout_ticks, void *up_dst,
+                             const void *up_src, size_t up_bytes, void *z0, size_t z0_words, void *z1,
+                             size_t z1_words, hipGraphExec_t *exec);
 
 // Kernel attribute set-up (dynamic LDS limits); call once per device.
 // `max_lds` is the device's LDS per workgroup; *usable receives the dynamic
 // LDS a launch may request.
 hipError_t engine_setup(size_t max_lds, size_t *usable);
 
-// Workgroups of the run kernel with `block` threads (block = 0: the batch
-// kernel) that fit on one CU with `lds` bytes of dynamic LDS.
-int engine_occupancy(size_t lds, int block);
+// Workgroups of the run (batch = false) or batch kernel with `block` threads
+// that fit on one CU with `lds` bytes of dynamic LDS.
+int engine_occupancy(size_t lds, int block, bool batch);
 
 }  // namespace hac

@@ -7,9 +7,11 @@
 //             the whole device.
 //   k_run     runs all n-1 merges of one instance on a group of g co-resident
 //             workgroups of 1024 threads (g = 1 for small n).
-//   k_batch   runs many independent instances, one workgroup of 256 threads
-//             each, taken largest-first from a queue; each workgroup does its
-//             instance's set-up itself.
+//   k_batch   runs many independent instances in one launch: the largest
+//             may each get a fixed group of workgroups (exchanging through
+//             their own slots), the rest take one workgroup each, largest
+//             first, from a queue; each workgroup does its instance's set-up
+//             itself.
 //
 // Data layout (one GPU, the whole matrix in HBM):
 //   * The n x n fp32 matrix is kept fully symmetric, row-major, so that both
@@ -486,7 +488,7 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // to the right of the old partner.
 template <int B>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
-                           uint64_t timeout, Stats &st) {
+                           uint64_t timeout, Stats &st, uint32_t epoch0 = 0) {
     constexpr int W = B / 64;
     constexpr int U = upd_batch<B>();
     const int n = I.n, link = I.link;
@@ -501,11 +503,13 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         s_nresc = 0;
     }
     __syncthreads();
-    fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[1][0]);  // candidates of epoch 1
+    // Merge s uses exchange epoch epoch0 + 1 + s (epochs below epoch0 + 1
+    // were used by the caller).
+    fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(epoch0 + 1) & 1][0]);
     int i_prev = -1;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
-        const uint32_t e = (uint32_t)s + 1u;
+        const uint32_t e = epoch0 + (uint32_t)s + 1u;
         const int b = e & 1;
         // The other parity's accumulators were last read before the last
         // barrier of the previous merge; clear them for epoch e+1.
@@ -696,43 +700,80 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
     flush_stats<B>(ctl, st);
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batch(const Instance *__restrict__ insts,
-                                                      const int32_t *__restrict__ order, int count,
-                                                      Control *ctl, uint64_t timeout) {
+// One batch instance on workgroup w of a group of g (g = 1: the whole
+// instance on this workgroup), including its set-up.  Returns when done.
+template <int B>
+__device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, Control *ctl,
+                               uint64_t timeout, Stats &st) {
+    const int n = I.n;
+    if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
+    const int own_ch = own_chunks(n, g, w);
+    const int own_cap = ((((n + 63) >> 6) + g - 1) / g) * 64;
+    const Lds L = carve(smem, n, own_cap);
+    for (int li = threadIdx.x; li < own_cap; li += B) L.cache[li] = kEmptyRow;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (int lq = 0; lq < own_ch; ++lq) {
+        const int R = chunk_of(lq, g, w);
+        setup_block<B>(I.D, n, R, L.tile, bad, [&](int r, uint64_t v) {
+            L.cache[lq * 64 + r] = v == kEmpty ? kEmptyRow : v;
+        });
+    }
+    // This workgroup's verdict on its part of the input, shared through LDS.
+    uint64_t okv = bad ? 0 : kEmpty, dummy = kEmpty;
+    block_min2<B>(okv, dummy);
+    if (okv == 0 && threadIdx.x == 0) atomicOr(I.status, kErrInput);
+    uint32_t epoch0 = 0;
+    if (g > 1) {
+        // The group's set-up (mirror, input check) must be complete and
+        // visible before any merge: one exchange with empty candidates, after
+        // which every thread reads the final status word.
+        if (threadIdx.x == 0) s_acc[1][0] = s_acc[1][1] = s_acc[1][2] = s_acc[1][3] = kEmpty;
+        __syncthreads();
+        if (!group_exchange<B>(I, g, w, 1u, ctl, timeout)) return;
+        epoch0 = 1;
+        if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
+    } else if (okv == 0) {
+        return;
+    }
+    init_masks<B>(L, n);  // size1 shares space with the tile
+    __syncthreads();
+    merge_loop<B>(I, g, w, L, ctl, timeout, st, epoch0);
+}
+
+// Batch: the first `ngroups` entries of `order` are run by fixed groups of
+// workgroups (task t on workgroups gbase[t] .. gbase[t]+gsize[t]-1); every
+// workgroup then takes the remaining entries one at a time from a queue
+// (largest instances first).  Launched cooperatively when ngroups > 0 so that
+// the members of a group are co-resident.
+template <int B>
+__global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
+                                             const int32_t *__restrict__ order, int count,
+                                             const int32_t *__restrict__ gbase,
+                                             const int32_t *__restrict__ gsize, int ngroups,
+                                             Control *ctl, uint64_t timeout) {
     extern __shared__ __align__(16) uint8_t smem[];
     Stats st;
+    const int wg = (int)blockIdx.x;
+    for (int t = 0; t < ngroups; ++t) {
+        const int base = gbase[t], g = gsize[t];
+        if (wg >= base && wg < base + g) {
+            const Instance I = insts[order[t]];
+            if (I.n > 1) batch_instance<B>(I, g, wg - base, smem, ctl, timeout, st);
+            __syncthreads();
+        }
+    }
     for (;;) {
-        if (threadIdx.x == 0) s_inst = (int)atomicAdd(&ctl->next, 1u);
+        if (threadIdx.x == 0) s_inst = ngroups + (int)atomicAdd(&ctl->next, 1u);
         __syncthreads();
         const int q = s_inst;
         __syncthreads();
         if (q >= count) break;
         const Instance I = insts[order[q]];
-        const int n = I.n;
-        if (n < 2) continue;
-        if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
-        const int nch = (n + 63) >> 6;
-        const Lds L = carve(smem, n, nch * 64);
-        for (int li = threadIdx.x; li < nch * 64; li += kBatchBlock) L.cache[li] = kEmptyRow;
-        __syncthreads();
-        uint32_t bad = 0;
-        for (int R = 0; R < nch; ++R)
-            setup_block<kBatchBlock>(I.D, n, R, L.tile, bad, [&](int r, uint64_t v) {
-                L.cache[R * 64 + r] = v == kEmpty ? kEmptyRow : v;
-            });
-        // Every thread's verdict on the input, shared through LDS.
-        uint64_t okv = bad ? 0 : kEmpty, dummy = kEmpty;
-        block_min2<kBatchBlock>(okv, dummy);
-        if (okv == 0) {
-            if (threadIdx.x == 0) atomicOr(I.status, kErrInput);
-            continue;
-        }
-        init_masks<kBatchBlock>(L, n);  // size1 shares space with the tile
-        __syncthreads();
-        merge_loop<kBatchBlock>(I, 1, 0, L, ctl, timeout, st);
+        if (I.n > 1) batch_instance<B>(I, 1, 0, smem, ctl, timeout, st);
         __syncthreads();
     }
-    flush_stats<kBatchBlock>(ctl, st);
+    flush_stats<B>(ctl, st);
 }
 
 __global__ void k_zero(uint32_t *p, size_t words) {
@@ -756,7 +797,8 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
     // Dynamic LDS may use what the static LDS of the kernels leaves free.
     size_t static_max = 0;
     const void *fns[] = {reinterpret_cast<const void *>(&k_run<256>), reinterpret_cast<const void *>(&k_run<512>),
-                         reinterpret_cast<const void *>(&k_run<1024>), reinterpret_cast<const void *>(&k_batch)};
+                         reinterpret_cast<const void *>(&k_run<1024>), reinterpret_cast<const void *>(&k_batch<256>),
+                         reinterpret_cast<const void *>(&k_batch<1024>)};
     for (const void *fn : fns) {
         hipFuncAttributes a;
         hipError_t e = hipFuncGetAttributes(&a, fn);
@@ -780,11 +822,15 @@ static const void *run_kernel(int block) {
     }
 }
 
-int engine_occupancy(size_t lds, int block) {
+static const void *batch_kernel(int block) {
+    return block == 1024 ? reinterpret_cast<const void *>(&k_batch<1024>)
+                         : reinterpret_cast<const void *>(&k_batch<256>);
+}
+
+int engine_occupancy(size_t lds, int block, bool batch) {
     int blocks = 0;
-    const void *fn = block == 0 ? reinterpret_cast<const void *>(&k_batch) : run_kernel(block);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, block == 0 ? kBatchBlock : block, lds) !=
-        hipSuccess) {
+    const void *fn = batch ? batch_kernel(block) : run_kernel(block);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, block, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
@@ -818,11 +864,92 @@ hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint
     return hipLaunchCooperativeKernel(run_kernel(block), dim3(g), dim3(block), args, (unsigned)lds, stream);
 }
 
-hipError_t launch_batch(const Instance *insts, const int32_t *order, int count, int grid,
-                        size_t lds, Control *ctl, uint64_t timeout_ticks, hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchBlock), lds, stream, insts, order, count, ctl,
-                       timeout_ticks);
-    return hipGetLastError();
+hipError_t launch_batch(const BatchLaunch &b, Control *ctl, uint64_t timeout_ticks, hipStream_t stream) {
+    const Instance *a0 = b.insts;
+    const int32_t *a1 = b.order;
+    int a2 = b.count;
+    const int32_t *a3 = b.gbase;
+    const int32_t *a4 = b.gsize;
+    int a5 = b.ngroups;
+    Control *a6 = ctl;
+    uint64_t a7 = timeout_ticks;
+    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
+    if (b.ngroups > 0)
+        return hipLaunchCooperativeKernel(batch_kernel(b.block), dim3(b.grid), dim3(b.block), args,
+                                          (unsigned)b.lds, stream);
+    return hipLaunchKernel(batch_kernel(b.block), dim3(b.grid), dim3(b.block), args, b.lds, stream);
+}
+
+static hipError_t add_zero_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *dep, size_t ndep,
+                                void *p, size_t words, void **argbuf) {
+    uint32_t **a0 = reinterpret_cast<uint32_t **>(argbuf[0]);
+    size_t *a1 = reinterpret_cast<size_t *>(argbuf[1]);
+    *a0 = reinterpret_cast<uint32_t *>(p);
+    *a1 = words;
+    unsigned grid = (unsigned)((words + 255) / 256);
+    if (grid > 1024) grid = 1024;
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void *>(&k_zero);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = argbuf;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, dep, ndep, &kp);
+}
+
+hipError_t build_batch_graph(const BatchLaunch &b, Control *ctl, uint64_t timeout_ticks, void *up_dst,
+                             const void *up_src, size_t up_bytes, void *z0, size_t z0_words, void *z1,
+                             size_t z1_words, hipGraphExec_t *exec) {
+    *exec = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    hipGraphNode_t last = nullptr, node = nullptr;
+    // Kernel arguments are copied when the node is added.
+    uint32_t *zp = nullptr;
+    size_t zw = 0;
+    void *zargs[] = {&zp, &zw};
+    e = hipGraphAddMemcpyNode1D(&node, g, nullptr, 0, up_dst, up_src, up_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        last = node;
+        if (z0_words) {
+            e = add_zero_node(g, &node, &last, 1, z0, z0_words, zargs);
+            if (e == hipSuccess) last = node;
+        }
+    }
+    if (e == hipSuccess && z1_words) {
+        e = add_zero_node(g, &node, &last, 1, z1, z1_words, zargs);
+        if (e == hipSuccess) last = node;
+    }
+    if (e == hipSuccess) {
+        const Instance *a0 = b.insts;
+        const int32_t *a1 = b.order;
+        int a2 = b.count;
+        const int32_t *a3 = b.gbase;
+        const int32_t *a4 = b.gsize;
+        int a5 = b.ngroups;
+        Control *a6 = ctl;
+        uint64_t a7 = timeout_ticks;
+        void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void *>(batch_kernel(b.block));
+        kp.gridDim = dim3(b.grid);
+        kp.blockDim = dim3(b.block);
+        kp.sharedMemBytes = (unsigned)b.lds;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        e = hipGraphAddKernelNode(&node, g, &last, 1, &kp);
+        if (e == hipSuccess && b.ngroups > 0) {
+            hipKernelNodeAttrValue v{};
+            v.cooperative = 1;
+            e = hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v);
+        }
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) *exec = nullptr;
+    return e;
 }
 
 }  // namespace hac

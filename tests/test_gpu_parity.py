@@ -227,6 +227,99 @@ def test_batch_ragged_edges(ctx, torch):
         assert _same(res[moff[k]:moff[k] + n - 1], exp), k
 
 
+def _batch_with_plan(ctx, torch, t, offs, ns, links, block, group):
+    import paper_1709_06816_amd as hac
+    ctx.set_option(hac.OPT_BATCH_BLOCK, block)
+    ctx.set_option(hac.OPT_BATCH_GROUP, group)
+    try:
+        res = ctx.batch(t, offs, ns, links, preserve=True)
+        return res, ctx.stats()
+    finally:
+        ctx.set_option(hac.OPT_BATCH_BLOCK, 0)
+        ctx.set_option(hac.OPT_BATCH_GROUP, 0)
+
+
+def test_batch_plans_identical(ctx, torch):
+    """Every launch plan (threads per workgroup, workgroups per large
+    instance) and the autotuned one give the same bytes; the instances that
+    ran on groups of workgroups match the oracle."""
+    spec = synth.batch_spec(count=40, n_lo=64, n_hi=4096, seed=777)
+    ns = spec.ns.copy()
+    ns[:3] = [4096, 2500, 2048]  # instances that qualify for groups
+    mats = [synth.batch_instance(int(n), int(s)) for n, s in zip(ns, spec.seeds)]
+    offs, total = synth.pack_offsets(ns)
+    packed = np.zeros(total, np.float32)
+    for k, m in enumerate(mats):
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+    t = torch.from_numpy(packed).cuda()
+    ref = None
+    for block, group in [(256, 1), (1024, 1), (256, 4), (1024, 8), (256, 16)]:
+        _say("batch plan block=%d group=%d" % (block, group))
+        res, st = _batch_with_plan(ctx, torch, t, offs, ns, spec.linkages, block, group)
+        assert st["block"] == block
+        assert st["group"] == group
+        if ref is None:
+            ref = res
+        else:
+            assert _same(res, ref), (block, group)
+    _say("batch autotuned")
+    res = ctx.batch(t, offs, ns, spec.linkages, preserve=True)
+    assert _same(res, ref)
+    assert ctx.stats()["block"] in (256, 1024)
+    res = ctx.batch(t, offs, ns, spec.linkages, preserve=True)  # cached plan
+    assert _same(res, ref)
+    assert np.array_equal(t.cpu().numpy(), packed)
+    moff, _ = synth.merge_offsets(ns)
+    for k in range(3):
+        n = int(ns[k])
+        exp = oracle.run_f32(mats[k], int(spec.linkages[k]))
+        assert _same(ref[moff[k]:moff[k] + n - 1], exp), (k, n)
+
+
+def test_batch_graph_replays(ctx, torch):
+    """The batch as one HIP graph: built once per layout, relaunched with new
+    inputs; every replay, with eager work in between, equals the stream
+    launch on the same input.  Also with groups (cooperative kernel node)."""
+    import paper_1709_06816_amd as hac
+    ns = np.array([2600, 900, 700, 300, 64, 65, 130, 33, 5, 2], np.int64)
+    links = np.array([1, 3, 2, 0, 1, 2, 3, 0, 1, 3], np.int32)
+    offs, total = synth.pack_offsets(ns)
+    inputs = []
+    for rep in range(3):
+        packed = np.zeros(total, np.float32)
+        for k, n in enumerate(ns):
+            packed[offs[k]:offs[k] + n * n] = synth.batch_instance(int(n), 9000 + 100 * rep + k).ravel()
+        inputs.append(torch.from_numpy(packed).cuda())
+    for group in (1, 4):
+        ctx.set_option(hac.OPT_BATCH_BLOCK, 256)
+        ctx.set_option(hac.OPT_BATCH_GROUP, group)
+        try:
+            ctx.set_option(hac.OPT_GRAPH, 0)
+            eager = [ctx.batch(t, offs, ns, links, preserve=True) for t in inputs]
+            assert ctx.stats()["graph"] == 0
+            ctx.set_option(hac.OPT_GRAPH, 1)
+            for rep in range(6):
+                k = rep % 3
+                _say("graph group=%d replay %d" % (group, rep))
+                res = ctx.batch(inputs[k], offs, ns, links, preserve=True)
+                st = ctx.stats()
+                assert st["graph"] == (2 if rep == 0 else 1), st["graph"]
+                assert st["group"] == group
+                assert _same(res, eager[k]), (group, rep)
+                # eager work between replays
+                m = synth.uniform_matrix(70, 300 + rep)
+                assert _same(_gpu_run(ctx, torch, m, "average"), oracle.run_f32(m, "average"))
+        finally:
+            ctx.set_option(hac.OPT_GRAPH, 1)
+            ctx.set_option(hac.OPT_BATCH_BLOCK, 0)
+            ctx.set_option(hac.OPT_BATCH_GROUP, 0)
+    moff, _ = synth.merge_offsets(ns)
+    packed = inputs[0].cpu().numpy()
+    for k, n in enumerate(ns):
+        m = packed[offs[k]:offs[k] + n * n].reshape(n, n)
+        assert _same(eager[0][moff[k]:moff[k] + n - 1], oracle.run_f32(m, int(links[k]))), k
+
+
 # ---------------------------------------------------------------------------
 # Larger sizes
 # ---------------------------------------------------------------------------
