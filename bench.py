@@ -142,6 +142,120 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
     }
 
 
+def serve_leg(torch, hac, ctx, requests, warmup, rate, budget_gb, big_n):
+    """Continuous batching: Poisson arrivals submitted open-loop from host
+    page-locked memory, latency = result on the host - scheduled arrival."""
+    import synth
+    n_hi = 16384
+    pool_n = 2
+    log("serve: generating %d pool matrices of n=%d" % (pool_n, n_hi))
+    pool = [torch.empty((n_hi, n_hi), dtype=torch.float32).pin_memory() for _ in range(pool_n)]
+    synth.serve_pool(pool_n, n_hi, out=[p.numpy() for p in pool])
+    big = None
+    if big_n:
+        log("serve: generating the n=%d instance" % big_n)
+        big = torch.empty((big_n, big_n), dtype=torch.float32).pin_memory()
+        synth.mixture_65536(n=big_n, out=big.numpy())
+    tr = synth.serve_trace(warmup + requests, rate=rate, n_hi=n_hi)
+    srv = hac.Server(ctx, budget_bytes=int(budget_gb * (1 << 30)), max_jobs=1024,
+                     max_n=max(n_hi, big_n or 0))
+    res = {}
+    try:
+        big_alone = None
+        if big is not None:
+            log("serve: n=%d alone" % big_n)
+            t0 = time.perf_counter()
+            tk = srv.submit(big, "average")
+            while True:
+                r = srv.poll(tk)
+                if r is not None:
+                    break
+                time.sleep(0.0005)
+            big_alone = (time.perf_counter() - t0, r)
+        big_at = warmup + requests // 4
+        log("serve: %d requests at %.0f/s (+%d warm-up)" % (requests, rate, warmup))
+        pending = {}
+        done_t = {}
+        results = {}
+        big_mix = None
+        t_start = time.perf_counter() + 0.05
+
+        def poll_all():
+            for k in list(pending):
+                r = srv.poll(pending[k])
+                if r is not None:
+                    done_t[k] = time.perf_counter()
+                    results[k] = r
+                    del pending[k]
+
+        for k in range(len(tr.ns)):
+            due = t_start + float(tr.arrivals[k])
+            while time.perf_counter() < due:
+                poll_all()
+                if due - time.perf_counter() > 0.002:
+                    time.sleep(0.0005)
+            n = int(tr.ns[k])
+            while True:
+                try:
+                    pending[k] = srv.submit(pool[k % pool_n][:n, :n], int(tr.linkages[k]))
+                    break
+                except hac.HacError as e:
+                    if e.code != hac.HAC_EBUSY:
+                        raise
+                    poll_all()
+            if big is not None and k == big_at:
+                big_mix = [time.perf_counter(), srv.submit(big, "average"), None]
+            if big_mix is not None and big_mix[2] is None:
+                r = srv.poll(big_mix[1])
+                if r is not None:
+                    big_mix[2] = (time.perf_counter() - big_mix[0], r)
+        while pending or (big_mix is not None and big_mix[2] is None):
+            poll_all()
+            if big_mix is not None and big_mix[2] is None:
+                r = srv.poll(big_mix[1])
+                if r is not None:
+                    big_mix[2] = (time.perf_counter() - big_mix[0], r)
+            time.sleep(0.0002)
+        meas = range(warmup, len(tr.ns))
+        lat = np.array([done_t[k] - (t_start + float(tr.arrivals[k])) for k in meas]) * 1000.0
+        span = max(done_t[k] for k in meas) - (t_start + float(tr.arrivals[warmup]))
+        mbytes = float(sum(4.0 * int(tr.ns[k]) ** 2 for k in meas))
+        # Alone vs in the mix: a sample of requests again, one at a time.
+        rng = np.random.default_rng(7)
+        sample = sorted(rng.choice(np.arange(warmup, len(tr.ns)), size=min(48, requests), replace=False))
+        same = True
+        for k in sample:
+            n = int(tr.ns[k])
+            tk = srv.submit(pool[k % pool_n][:n, :n], int(tr.linkages[k]))
+            while True:
+                r = srv.poll(tk)
+                if r is not None:
+                    break
+                time.sleep(0.0002)
+            same &= r.tobytes() == results[k].tobytes()
+        st = srv.stats()
+        res = {
+            "workload": "Poisson arrivals at %.0f/s, n log-uniform on [256, %d], linkage uniform over 4, "
+                        "Gaussian mixtures in R^16 (top-left blocks of %d page-locked %d-point mixtures), "
+                        "HBM budget %.0f GB" % (rate, n_hi, pool_n, n_hi, budget_gb),
+            "requests": requests, "warmup": warmup,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "jobs_per_s": requests / span, "offered_jobs_per_s": rate,
+            "matrix_gb_per_s": mbytes / span / 1e9,
+            "alone_vs_mix_identical": bool(same), "alone_vs_mix_sample": len(sample),
+            "peak_gb": st["peak_bytes"] / 1e9, "kernel_launches": st["kernel_launches"],
+            "workgroups": st["workgroups"], "block": st["block"],
+        }
+        if big is not None:
+            res["big"] = {"n": big_n, "linkage": "average",
+                          "alone_s": big_alone[0], "in_mix_latency_s": big_mix[2][0],
+                          "identical": bool(big_alone[1].tobytes() == big_mix[2][1].tobytes())}
+    finally:
+        srv.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +267,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-big-n", type=int, default=65536, help="0: no big instance")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a reference kernel of known "
                          "traffic for the HBM byte counters)")
@@ -238,6 +358,12 @@ def main():
     if not args.no_batch:
         log("batch leg")
         result["batched"] = batch_leg(torch, hac, ctx, args.batch_count, 64, 4096, reps=3)
+    if not args.no_serve:
+        del src
+        torch.cuda.empty_cache()
+        log("serving leg")
+        result["serving"] = serve_leg(torch, hac, ctx, args.serve_requests, args.serve_warmup,
+                                      args.serve_rate, args.serve_budget_gb, args.serve_big_n)
     if not args.no_cpu:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(d, link, n, args.cpu_budget, merges)

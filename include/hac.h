@@ -66,7 +66,7 @@ typedef enum {
     HAC_ENOMEM = -3,    /* device memory for the workspace could not be allocated */
     HAC_EDEVICE = -4,   /* a HIP call failed; see hac_last_error() */
     HAC_ENODEV = -5,    /* no usable gfx950 device */
-    HAC_EBUSY = -6,     /* reserved */
+    HAC_EBUSY = -6,     /* hac_submit: the server already holds max_jobs jobs */
     HAC_ETIMEDOUT = -7, /* the persistent kernel's watchdog fired */
     HAC_EINTERNAL = -8  /* an invariant of the algorithm was broken on the device */
 } hac_status;
@@ -203,6 +203,68 @@ typedef struct {
     int32_t graph;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
+
+/*
+ * Serving with continuous batching.  Not a paper algorithm: many independent
+ * clustering jobs (each the computation described above) share one GPU.
+ *
+ * A server owns an HBM arena of hbm_budget_bytes and a persistent kernel on
+ * its own streams.  Jobs are admitted in arrival order as soon as the arena
+ * holds their matrix and workspace; their matrix is copied host-to-device
+ * on a copy stream, then published to the running kernel, whose workgroups
+ * take jobs as they free up, so jobs that arrive while others run overlap
+ * with them on the device.  Jobs with n above 2048 run on a group of
+ * workgroups.  A job's merge list is byte-identical to hac_run on the same
+ * matrix, whatever else runs beside it.  A host thread of the server drives
+ * admission, publication and completion; the kernel stops after a short
+ * idle period and is relaunched on demand.
+ *
+ * hac_server_create -- ctx: a context (its device and HAC_OPT_TIMEOUT_MS are
+ *   read at creation; the server keeps no reference; the timeout bounds the
+ *   kernel's waits, default 120 s, and how long the kernel waits idle for a
+ *   stop from the host before it stops by itself, default 60 s);
+ *   hbm_budget_bytes: arena size
+ *   (allocated at once); max_jobs: jobs held at a time, 1..4096 (submitted
+ *   and not yet returned by hac_poll); max_n: largest n a job may have
+ *   (2..HAC_MAX_N), which fixes the kernel's LDS per workgroup.
+ *   Errors: HAC_EINVAL, HAC_ENOMEM (arena), HAC_EDEVICE.
+ * hac_submit -- queue one job.  host_dist: host fp32 matrix, row-major with
+ *   leading dimension ld >= n (elements); the top-left n x n block is the
+ *   job's matrix, read under the same conventions as hac_run.  The server
+ *   reads host_dist until the job is complete: keep it valid and unchanged
+ *   until hac_poll reports done (page-locked memory gives the full copy
+ *   rate).  *ticket identifies the job.  Returns HAC_EBUSY if max_jobs jobs
+ *   are held, HAC_ENOMEM if the job alone exceeds the budget, HAC_EINVAL for
+ *   bad arguments, or the server's error if it has failed.
+ * hac_poll -- *done = 1 and the job's n-1 records in out (host memory) once
+ *   it is complete; the ticket is then released and its status returned
+ *   (HAC_OK, HAC_EINPUT, HAC_ETIMEDOUT, ...).  *done = 0 while it runs.
+ *   out may be NULL to discard the records.  Unknown ticket: HAC_EINVAL.
+ * hac_server_destroy -- wait for admitted jobs to finish, stop the kernel,
+ *   free everything.  Held tickets become invalid.
+ * hac_server_get_stats -- counters of the server (see hac_server_stats).
+ * hac_server_last_error -- text of the server's last error; valid until the
+ *   next call on the server.
+ * Calls on one server may come from any host threads.
+ */
+typedef struct hac_server hac_server;
+typedef struct {
+    int64_t submitted;
+    int64_t completed;
+    int64_t waiting;          /* queued, not yet admitted */
+    int64_t running;          /* admitted (copying or on the device), not complete */
+    int64_t bytes_in_use;     /* arena bytes held by admitted jobs */
+    int64_t peak_bytes;       /* largest bytes_in_use so far */
+    int64_t kernel_launches;  /* launches of the persistent kernel */
+    int32_t workgroups;       /* workgroups of that kernel */
+    int32_t block;            /* threads per workgroup */
+} hac_server_stats;
+int hac_server_create(hac_ctx *ctx, size_t hbm_budget_bytes, int32_t max_jobs, int32_t max_n, hac_server **out);
+int hac_submit(hac_server *srv, const float *host_dist, int64_t ld, int32_t n, int32_t linkage, uint64_t *ticket);
+int hac_poll(hac_server *srv, uint64_t ticket, hac_merge *out, int32_t *done);
+int hac_server_get_stats(hac_server *srv, hac_server_stats *out);
+const char *hac_server_last_error(hac_server *srv);
+int hac_server_destroy(hac_server *srv);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ import threading
 
 import numpy as np
 
-__all__ = ["HacError", "Context", "run", "batch", "to_linkage_matrix", "MERGE_DTYPE",
+__all__ = ["HacError", "Context", "Server", "run", "batch", "to_linkage_matrix", "MERGE_DTYPE",
            "LINKAGES", "library_path", "load_library"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -46,7 +46,8 @@ _STATUS_NAMES = {
 
 # Symbols the library must export (one per declaration in include/hac.h).
 EXPORTS = ("hac_create", "hac_destroy", "hac_run", "hac_batch", "hac_sync", "hac_last_error",
-           "hac_set_option", "hac_get_stats")
+           "hac_set_option", "hac_get_stats", "hac_server_create", "hac_submit", "hac_poll",
+           "hac_server_get_stats", "hac_server_last_error", "hac_server_destroy")
 
 
 class HacError(RuntimeError):
@@ -66,6 +67,14 @@ class _Stats(ctypes.Structure):
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("waiting", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("kernel_launches", ctypes.c_int64), ("workgroups", ctypes.c_int32),
+                ("block", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -97,8 +106,15 @@ def load_library():
         lib.hac_last_error.restype = ctypes.c_char_p
         lib.hac_set_option.argtypes = [vp, i32, i64]
         lib.hac_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        lib.hac_server_create.argtypes = [vp, ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)]
+        lib.hac_submit.argtypes = [vp, vp, i64, i32, i32, ctypes.POINTER(ctypes.c_uint64)]
+        lib.hac_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(i32)]
+        lib.hac_server_get_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+        lib.hac_server_last_error.argtypes = [vp]
+        lib.hac_server_last_error.restype = ctypes.c_char_p
+        lib.hac_server_destroy.argtypes = [vp]
         for name in EXPORTS:
-            if name != "hac_last_error":
+            if name not in ("hac_last_error", "hac_server_last_error"):
                 getattr(lib, name).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -241,6 +257,83 @@ class Context:
 
     def sync(self):
         self._check(self._lib.hac_sync(self._h))
+
+
+class Server:
+    """Continuous-batching server (hac_server_create ... hac_server_destroy).
+
+    ``submit`` takes a host float32 matrix (2-D, rows contiguous; a view of
+    the top-left n x n block of a larger array is fine) and returns a ticket;
+    the array is kept referenced until the job is returned by ``poll``.
+    ``poll`` returns None while the job runs, else its MERGE_DTYPE[n-1]
+    records (raising HacError if the job failed)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_jobs: int = 1024, max_n: int = 16384):
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        rc = self._lib.hac_server_create(ctx._h, int(budget_bytes), int(max_jobs), int(max_n),
+                                         ctypes.byref(h))
+        if rc != HAC_OK:
+            raise HacError(rc, "hac_server_create")
+        self._h = h
+        self._held = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hac_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != HAC_OK:
+            msg = self._lib.hac_server_last_error(self._h)
+            raise HacError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def submit(self, dist, linkage) -> int:
+        """Queue the top-left n x n block of ``dist`` (host float32, 2-D)."""
+        a = dist
+        if isinstance(a, np.ndarray):
+            if a.dtype != np.float32 or a.ndim != 2 or a.shape[0] != a.shape[1] or a.strides[1] != 4:
+                raise ValueError("expected a square float32 array with contiguous rows")
+            n, ld, ptr = a.shape[0], a.strides[0] // 4, a.ctypes.data
+        else:  # torch CPU tensor (e.g. a pinned one or a view of it)
+            import torch
+            if a.dtype != torch.float32 or a.dim() != 2 or a.shape[0] != a.shape[1] or a.stride(1) != 1 \
+                    or a.is_cuda:
+                raise ValueError("expected a square float32 host tensor with contiguous rows")
+            n, ld, ptr = a.shape[0], a.stride(0), a.data_ptr()
+        t = ctypes.c_uint64()
+        self._check(self._lib.hac_submit(self._h, ctypes.c_void_p(ptr), int(ld), int(n), _link(linkage),
+                                         ctypes.byref(t)), "hac_submit")
+        self._held[t.value] = (a, int(n))
+        return t.value
+
+    def poll(self, ticket: int):
+        a, n = self._held[ticket]
+        out = np.zeros(max(n - 1, 1), MERGE_DTYPE)
+        done = ctypes.c_int32(0)
+        rc = self._lib.hac_poll(self._h, ctypes.c_uint64(ticket), out.ctypes.data, ctypes.byref(done))
+        if done.value:
+            del self._held[ticket]
+        self._check(rc, "hac_poll")
+        return out[:n - 1] if done.value else None
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        self._check(self._lib.hac_server_get_stats(self._h, ctypes.byref(st)), "hac_server_get_stats")
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
 
 
 _default = None

@@ -6,8 +6,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhac.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hac_engine.hip", "hac_api.cpp")]
-HEADERS = [os.path.join(HERE, "csrc", "hac_engine.h"), os.path.join(ROOT, "include", "hac.h")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hac_engine.hip", "hac_api.cpp", "hac_serve.cpp")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("hac_engine.h", "hac_ctx_info.h", "hac_arena.h")] + [
+    os.path.join(ROOT, "include", "hac.h")]
 
 # Floating point: no contraction into FMA, no fast-math, denormals kept, and no
 # packed fp32 instructions (the update arithmetic must round each operation
@@ -16,7 +17,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fno-fast-math", "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-command-line-argument",
+    "-Wall", "-Wno-unused-command-line-argument", "-pthread",
 ]
 
 

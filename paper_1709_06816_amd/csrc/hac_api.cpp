@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "hac.h"
+#include "hac_ctx_info.h"
 #include "hac_engine.h"
 
 namespace {
@@ -390,6 +391,16 @@ int batch_autotune(hac_ctx *c, float *packed, int64_t extent, const int64_t *off
 }
 
 }  // namespace
+
+namespace hac {
+void ctx_info(const hac_ctx *c, CtxInfo *out) {
+    out->device = c->device;
+    out->cus = c->cus;
+    out->wallclock_khz = c->wallclock_khz;
+    out->lds_max = c->lds_max;
+    out->timeout_ms = c->opt_timeout_ms;
+}
+}  // namespace hac
 
 extern "C" {
 

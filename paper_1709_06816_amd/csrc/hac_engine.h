@@ -100,6 +100,53 @@ hipError_t build_batch_graph(const BatchLaunch &b, Control *ctl, uint64_t timeou
                              const void *up_src, size_t up_bytes, void *z0, size_t z0_words, void *z1,
                              size_t z1_words, hipGraphExec_t *exec);
 
+// Serving: a persistent kernel runs jobs that the host publishes as entries
+// of a ring in fine-grained host memory, one entry per workgroup of a job.
+// Per job slot (index `job`), device memory holds the status word, the
+// count of members done and the group's exchange slots; they are zero when
+// a job starts and the last member to finish clears them again.
+struct ServeEntry {
+    Instance inst;        // inst.D: device matrix; inst.out: records (page-locked host memory);
+                          // inst.status: the job slot's words; inst.slots: its exchange slots (g > 1)
+    const float *src;     // the job's matrix in page-locked host memory (device address)
+    int64_t ld;           // its leading dimension (elements)
+    int32_t g;            // workgroups on the job
+    int32_t rank;         // this entry's workgroup within the job
+    uint32_t job;         // job slot: index of its completion word
+    uint32_t seq;         // completion word once done: seq << 32 | status
+};
+static_assert(sizeof(ServeEntry) % 8 == 0, "entries are read as 64-bit words");
+
+struct ServeHost {        // fine-grained (coherent) host memory
+    unsigned long long tail;   // entries published (release store by the host)
+    uint32_t stop;             // set by the host when nothing is outstanding
+    uint32_t pad;
+};
+
+struct ServeDev {         // device memory, set by the host before each launch
+    unsigned long long head;   // next entry to claim
+    unsigned long long tail;   // device copy of ServeHost::tail
+    uint32_t token;            // 1 while a workgroup polls host memory
+    uint32_t stop;             // device copy of ServeHost::stop
+    uint32_t exits;            // workgroups that have left the kernel
+    uint32_t self_stops;       // idle stops raised by the kernel itself
+    unsigned long long claims; // entries taken
+};
+
+struct ServeLaunch {
+    ServeHost *host;
+    const ServeEntry *ring;    // fine-grained host memory, `cap` entries
+    uint32_t cap;
+    unsigned long long *done;  // fine-grained host memory, one completion word per job slot
+    ServeDev *dev;
+    int block;                 // 256 or 1024
+    int grid;                  // workgroups (all co-resident)
+    size_t lds;
+    uint64_t idle_ticks;       // a workgroup idle this long stops the kernel by itself
+};
+hipError_t launch_serve(const ServeLaunch &s, Control *ctl, uint64_t timeout_ticks, hipStream_t stream);
+int serve_occupancy(size_t lds, int block);
+
 // Kernel attribute set-up (dynamic LDS limits); call once per device.
 // `max_lds` is the device's LDS per workgroup; *usable receives the dynamic
 // LDS a launch may request.

@@ -92,6 +92,27 @@ __device__ __forceinline__ float lw_update(int link, float dki, float dkj, float
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+// Matrix loads of the merge loop that may see entries another workgroup of
+// the group wrote inside the same launch.  When the set-up (mirror, copy-in)
+// runs in the same kernel as the merges and several workgroups share an
+// instance, these are device-scope loads (coh = true): plain loads were
+// measured to return stale entries there despite the exchange's
+// release/acquire.  The single-instance path, whose set-up is a separate
+// kernel, and workgroups alone on an instance use plain loads.
+__device__ __forceinline__ float ld_f32(const float *p, bool coh) {
+    return coh ? __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT))
+               : *p;
+}
+__device__ __forceinline__ float4 ld_f32x4(const float *p, bool coh) {
+    if (!coh) return *reinterpret_cast<const float4 *>(p);
+    const unsigned long long *q = reinterpret_cast<const unsigned long long *>(p);
+    const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float4(__uint_as_float((uint32_t)a), __uint_as_float((uint32_t)(a >> 32)),
+                       __uint_as_float((uint32_t)b), __uint_as_float((uint32_t)(b >> 32)));
+}
+
 // Wave-wide reductions from the ROCm device library (DPP lane moves, no LDS
 // round trips); the result is uniform across the wave.  Call with every lane
 // of the wave active.
@@ -390,7 +411,7 @@ __device__ void init_masks(const Lds &L, int n) {
 // minima into the entry with LDS atomics, so no barrier is needed per row.
 template <int B>
 __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, const Lds &L,
-                            uint32_t nresc, int skip, unsigned long long &elems) {
+                            uint32_t nresc, int skip, unsigned long long &elems, bool coh) {
     constexpr int W = B / 64, U = seg_unroll<B>();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int base = 0;
@@ -402,7 +423,6 @@ __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, co
         int nseg;
         if ((n & 3) == 0) {
             // 16-byte loads over quads q0 .. n/4-1; row starts are aligned.
-            const float4 *r4 = reinterpret_cast<const float4 *>(row);
             const int q0 = (k + 1) >> 2, nq = n >> 2;
             nseg = (nq - q0 + 64 * U - 1) / (64 * U);
             for (int sg = first_sg; sg < nseg; sg += W) {
@@ -410,7 +430,7 @@ __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, co
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int q = q0 + sg * 64 * U + u * 64 + lane;
-                    x[u] = q < nq ? r4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    x[u] = q < nq ? ld_f32x4(row + 4 * q, coh) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
                 uint64_t best = kEmpty;
 #pragma unroll
@@ -438,7 +458,7 @@ __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, co
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int l = l0 + sg * 64 * U + u * 64 + lane;
-                    x[u] = l < n ? row[l] : 0.0f;
+                    x[u] = l < n ? ld_f32(row + l, coh) : 0.0f;
                 }
                 uint64_t best = kEmpty;
 #pragma unroll
@@ -488,7 +508,7 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // to the right of the old partner.
 template <int B>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
-                           uint64_t timeout, Stats &st, uint32_t epoch0 = 0) {
+                           uint64_t timeout, Stats &st, uint32_t epoch0, bool coh) {
     constexpr int W = B / 64;
     constexpr int U = upd_batch<B>();
     const int n = I.n, link = I.link;
@@ -563,8 +583,8 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         for (int u = 0; u < U; ++u) {
             const int lq = wv + u * W;
             const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-            a[u] = k < n ? Di[k] : 0.0f;
-            bv[u] = k < n ? Dj[k] : 0.0f;
+            a[u] = k < n ? ld_f32(Di + k, coh) : 0.0f;
+            bv[u] = k < n ? ld_f32(Dj + k, coh) : 0.0f;
         }
         // ---- retire j (Section 5.3 step 6); queue rows whose partner is i or j
         if (tid == 0) {
@@ -588,7 +608,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         __syncthreads();
         if (prof) st.lap(kPhUpdate);
         const uint32_t nresc = s_nresc;
-        if (nresc) rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems);
+        if (nresc) rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems, coh);
         if (prof) st.lap(kPhRescan);
 
         // ---- Lance-Williams update of row/column i (Section 4 step 3) -----
@@ -605,8 +625,8 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 for (int u = 0; u < U; ++u) {
                     const int lq = lq0 + u * W;
                     const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-                    a[u] = k < n ? Di[k] : 0.0f;
-                    bv[u] = k < n ? Dj[k] : 0.0f;
+                    a[u] = k < n ? ld_f32(Di + k, coh) : 0.0f;
+                    bv[u] = k < n ? ld_f32(Dj + k, coh) : 0.0f;
                 }
             }
 #pragma unroll
@@ -696,7 +716,7 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
         L.cache[li] = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmptyRow;
     }
     __syncthreads();
-    merge_loop<B>(I, g, w, L, ctl, timeout, st);
+    merge_loop<B>(I, g, w, L, ctl, timeout, st, 0u, false);
     flush_stats<B>(ctl, st);
 }
 
@@ -704,7 +724,7 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
 // instance on this workgroup), including its set-up.  Returns when done.
 template <int B>
 __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, Control *ctl,
-                               uint64_t timeout, Stats &st) {
+                               uint64_t timeout, Stats &st, uint32_t epoch_base = 0) {
     const int n = I.n;
     if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
     const int own_ch = own_chunks(n, g, w);
@@ -728,17 +748,18 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
         // The group's set-up (mirror, input check) must be complete and
         // visible before any merge: one exchange with empty candidates, after
         // which every thread reads the final status word.
-        if (threadIdx.x == 0) s_acc[1][0] = s_acc[1][1] = s_acc[1][2] = s_acc[1][3] = kEmpty;
+        const uint32_t e = epoch_base + 1u;
+        if (threadIdx.x == 0) s_acc[e & 1][0] = s_acc[e & 1][1] = s_acc[e & 1][2] = s_acc[e & 1][3] = kEmpty;
         __syncthreads();
-        if (!group_exchange<B>(I, g, w, 1u, ctl, timeout)) return;
-        epoch0 = 1;
+        if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+        epoch0 = e;
         if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
     } else if (okv == 0) {
         return;
     }
     init_masks<B>(L, n);  // size1 shares space with the tile
     __syncthreads();
-    merge_loop<B>(I, g, w, L, ctl, timeout, st, epoch0);
+    merge_loop<B>(I, g, w, L, ctl, timeout, st, epoch0, g > 1);
 }
 
 // Batch: the first `ngroups` entries of `order` are run by fixed groups of
@@ -776,6 +797,206 @@ __global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
     flush_stats<B>(ctl, st);
 }
 
+// Serving: claim the next published entry (thread 0 only).  One workgroup
+// at a time holds the token and polls the host's tail, mirroring it into
+// device memory where the others poll it cheaply.  Returns false once the
+// host has asked to stop and no entry is left.
+__device__ bool serve_claim(ServeHost *host, const ServeEntry *ring, uint32_t cap, ServeDev *dev,
+                            ServeEntry *out, uint64_t idle_ticks) {
+    // Idle workgroups poll with relaxed loads only: an acquire would
+    // invalidate their XCD's L2 on every poll, under the feet of the jobs
+    // running beside them.  Ordering is taken once, after a claim or a stop.
+    bool poller = false;
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t it = 1;; ++it) {
+        const uint32_t stop = __hip_atomic_load(&dev->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (stop) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // stop is read before tail: the poller raises stop only after it has
+        // mirrored the final tail, so a stopped reader sees every entry.
+        const unsigned long long t = __hip_atomic_load(&dev->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long h = __hip_atomic_load(&dev->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < t) {
+            if (__hip_atomic_compare_exchange_strong(&dev->head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                if (poller) __hip_atomic_store(&dev->token, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&dev->claims, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                // The entry lives in host memory: read it word by word with
+                // system-scope loads (never through a cache).
+                const unsigned long long *src =
+                    reinterpret_cast<const unsigned long long *>(ring + (size_t)(h % cap));
+                unsigned long long *dst = reinterpret_cast<unsigned long long *>(out);
+                for (int q = 0; q < (int)(sizeof(ServeEntry) / 8); ++q)
+                    dst[q] = __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                return true;
+            }
+            continue;
+        }
+        if (stop) {
+            if (poller) __hip_atomic_store(&dev->token, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if (!poller) {
+            uint32_t z = 0;
+            poller = __hip_atomic_compare_exchange_strong(&dev->token, &z, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (poller) {
+            const unsigned long long ht = __hip_atomic_load(&host->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (ht > t) {
+                __hip_atomic_fetch_max(&dev->tail, ht, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                continue;
+            }
+            if (__hip_atomic_load(&host->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                // The host publishes nothing after asking to stop; re-read
+                // its tail once more so that the mirror is final.
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                const unsigned long long hf =
+                    __hip_atomic_load(&host->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_fetch_max(&dev->tail, hf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&dev->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                continue;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        } else {
+            __builtin_amdgcn_s_sleep(32);
+        }
+        // Safety net: the host stops an idle kernel long before this; if it
+        // never does, stop as if it had (entries are still taken first).
+        if ((it & 255u) == 0 && wall_clock64() - t0 > idle_ticks) {
+            __hip_atomic_fetch_add(&dev->self_stops, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&dev->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Host memory is read with system-scope loads: the same host buffer may hold
+// another job's matrix than when this XCD's L2 last cached it.
+__device__ __forceinline__ float ld_host(const float *p) {
+    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_SYSTEM));
+}
+
+// Serving: workgroup w of a job's g copies from the job's host matrix
+// (page-locked memory read over the bus; leading dimension ld) the part of
+// the strict upper triangle that it will itself read: the whole upper part
+// of its own rows (its set-up reads them) and, of every other row, the
+// entries in its own columns (its Lance-Williams updates read them).  Every
+// matrix entry a workgroup later reads was thus written by that workgroup
+// (or holds the same input value written by two), so no plain data crosses
+// workgroups, as in the rest of the merge loop.  One wave per row, up to 16
+// loads in flight per lane.
+template <int B>
+__device__ void copy_in_upper(const float *src, int64_t ld, float *D, int n, int g, int w) {
+    constexpr int W = B / 64;
+    constexpr int U = 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int own_ch = own_chunks(n, g, w);
+    for (int i = wv; i < n - 1; i += W) {
+        const float *sr = src + (size_t)i * (size_t)ld;
+        float *dr = D + (size_t)i * (size_t)n;
+        if (owner_of_row(i, g) == w) {
+            for (int c0 = i + 1; c0 < n; c0 += 64 * U) {
+                float v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = c0 + lane + 64 * u;
+                    v[u] = c < n ? ld_host(sr + c) : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = c0 + lane + 64 * u;
+                    if (c < n) dr[c] = v[u];
+                }
+            }
+        } else {
+            for (int lq0 = 0; lq0 < own_ch; lq0 += U) {
+                float v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int lq = lq0 + u;
+                    const int c = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
+                    v[u] = (c > i && c < n) ? ld_host(sr + c) : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int lq = lq0 + u;
+                    const int c = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
+                    if (c > i && c < n) dr[c] = v[u];
+                }
+            }
+        }
+    }
+}
+
+// Serving kernel: every workgroup takes entries until the host stops it.
+// A job on g workgroups has g consecutive entries; members are taken in
+// publication order, so the earliest incomplete job always gets its members
+// as workgroups free up.  The last member to finish clears the job slot's
+// device words (after every member has passed the last exchange) and
+// publishes seq << 32 | status in host memory after a system-scope release.
+template <int B>
+__global__ __launch_bounds__(B) void k_serve(ServeHost *host, const ServeEntry *ring, uint32_t cap,
+                                             unsigned long long *done, ServeDev *dev, Control *ctl,
+                                             uint64_t timeout, uint64_t idle_ticks) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ ServeEntry s_job;
+    __shared__ uint32_t s_status;
+    Stats st;
+    for (;;) {
+        if (threadIdx.x == 0) s_inst = serve_claim(host, ring, cap, dev, &s_job, idle_ticks) ? 1 : 0;
+        __syncthreads();
+        if (s_inst == 0) break;
+        // The entry is the same for the whole workgroup: keep it in scalar
+        // registers.  s_job stays unchanged until the next claim.
+        ServeEntry e;
+        {
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(&s_job);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(&e);
+            for (int q = 0; q < (int)(sizeof(ServeEntry) / 4); ++q)
+                dst[q] = (uint32_t)__builtin_amdgcn_readfirstlane((int)src[q]);
+        }
+        // Host memory may have changed since this kernel last read it: drop
+        // cached lines before reading the job's matrix.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        if (e.inst.n > 1) {
+            copy_in_upper<B>(e.src, e.ld, e.inst.D, e.inst.n, e.g, e.rank);
+            __syncthreads();
+            batch_instance<B>(e.inst, e.g, e.rank, smem, ctl, timeout, st);
+        }
+        __syncthreads();
+        uint32_t *words = e.inst.status;  // [0] status, [1] members done
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            const uint32_t prev = __hip_atomic_fetch_add(words + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            s_inst = prev + 1 == (uint32_t)e.g ? 2 : 1;
+            if (s_inst == 2) s_status = __hip_atomic_load(words, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (s_inst == 2) {
+            // Every member is past its last exchange: clear the slots for the
+            // job slot's next use, then the words, then publish.
+            if (e.g > 1) {
+                const int words64 = 2 * (e.g + 1) * kSlotStride;
+                for (int q = threadIdx.x; q < words64; q += B) {
+                    if ((q % kSlotStride) < 3)
+                        __hip_atomic_store(e.inst.slots + q, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(words, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(words + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                __hip_atomic_store(done + e.job, ((unsigned long long)e.seq << 32) | s_status, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    }
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&dev->exits, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    flush_stats<B>(ctl, st);
+}
+
 __global__ void k_zero(uint32_t *p, size_t words) {
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < words;
          q += (size_t)gridDim.x * blockDim.x)
@@ -798,7 +1019,8 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
     size_t static_max = 0;
     const void *fns[] = {reinterpret_cast<const void *>(&k_run<256>), reinterpret_cast<const void *>(&k_run<512>),
                          reinterpret_cast<const void *>(&k_run<1024>), reinterpret_cast<const void *>(&k_batch<256>),
-                         reinterpret_cast<const void *>(&k_batch<1024>)};
+                         reinterpret_cast<const void *>(&k_batch<1024>), reinterpret_cast<const void *>(&k_serve<256>),
+                         reinterpret_cast<const void *>(&k_serve<1024>)};
     for (const void *fn : fns) {
         hipFuncAttributes a;
         hipError_t e = hipFuncGetAttributes(&a, fn);
@@ -835,6 +1057,34 @@ int engine_occupancy(size_t lds, int block, bool batch) {
         return 1;
     }
     return blocks;
+}
+
+static const void *serve_kernel(int block) {
+    return block == 1024 ? reinterpret_cast<const void *>(&k_serve<1024>)
+                         : reinterpret_cast<const void *>(&k_serve<256>);
+}
+
+int serve_occupancy(size_t lds, int block) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, serve_kernel(block), block, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return blocks;
+}
+
+hipError_t launch_serve(const ServeLaunch &sl, Control *ctl, uint64_t timeout_ticks, hipStream_t stream) {
+    ServeHost *a0 = sl.host;
+    const ServeEntry *a1 = sl.ring;
+    uint32_t a2 = sl.cap;
+    unsigned long long *a3 = sl.done;
+    ServeDev *a4 = sl.dev;
+    Control *a5 = ctl;
+    uint64_t a6 = timeout_ticks;
+    uint64_t a7 = sl.idle_ticks;
+    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
+    return hipLaunchCooperativeKernel(serve_kernel(sl.block), dim3(sl.grid), dim3(sl.block), args,
+                                      (unsigned)sl.lds, stream);
 }
 
 hipError_t launch_zero(void *p, size_t words, hipStream_t stream) {

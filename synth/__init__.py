@@ -199,6 +199,28 @@ def serve_trace(count: int, rate: float = 200.0, n_lo: int = 256, n_hi: int = 16
     return ServeTrace(np.cumsum(gaps), ns, links, seeds)
 
 
+def serve_pool(count: int = 2, n: int = 16384, seed: int = BASE_SEED + 5, out=None) -> list:
+    """Matrices that serving requests are cut from: each is the distance
+    matrix of n points of a Gaussian mixture in R^16 (K ~ U{2..32} centres,
+    sigma ~ U[0.5, 2]), so its top-left m x m block is the matrix of m points
+    drawn from that mixture.  ``out``: optional list of (n, n) float32
+    arrays to fill (e.g. views of page-locked buffers)."""
+    mats = []
+    for p in range(count):
+        rng = np.random.default_rng(seed * 1000 + 7919 + p)
+        k = int(rng.integers(2, 33))
+        pts = gaussian_mixture(rng, n, 16, k, 0.5, 2.0)
+        mats.append(euclidean_matrix(pts, out=None if out is None else out[p]))
+    return mats
+
+
+def mixture_65536(seed: int = BASE_SEED + 6, n: int = 65536, out=None) -> np.ndarray:
+    """n=65536 points in R^16, 64 clusters with sigma ~ U[0.5, 2] (16 GiB
+    fp32 matrix; pass ``out`` to fill a preallocated (n, n) float32 array)."""
+    rng = np.random.default_rng(seed)
+    return euclidean_matrix(gaussian_mixture(rng, n, 16, 64, 0.5, 2.0), out=out)
+
+
 # ---------------------------------------------------------------------------
 # Small structured matrices for edge cases
 # ---------------------------------------------------------------------------
