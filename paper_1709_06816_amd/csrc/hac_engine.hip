@@ -803,9 +803,10 @@ __global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
 // host has asked to stop and no entry is left.
 __device__ bool serve_claim(ServeHost *host, const ServeEntry *ring, uint32_t cap, ServeDev *dev,
                             ServeEntry *out, uint64_t idle_ticks) {
-    // Idle workgroups poll with relaxed loads only: an acquire would
-    // invalidate their XCD's L2 on every poll, under the feet of the jobs
-    // running beside them.  Ordering is taken once, after a claim or a stop.
+    // Idle workgroups poll rarely, with relaxed loads only (an acquire would
+    // invalidate their XCD's L2 on every poll), and try for the poller token
+    // only when it looks free.  Ordering is taken once, after a claim or a
+    // stop.
     bool poller = false;
     const uint64_t t0 = wall_clock64();
     for (uint32_t it = 1;; ++it) {
@@ -836,7 +837,7 @@ __device__ bool serve_claim(ServeHost *host, const ServeEntry *ring, uint32_t ca
             if (poller) __hip_atomic_store(&dev->token, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
-        if (!poller) {
+        if (!poller && __hip_atomic_load(&dev->token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
             uint32_t z = 0;
             poller = __hip_atomic_compare_exchange_strong(&dev->token, &z, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT);
@@ -859,7 +860,10 @@ __device__ bool serve_claim(ServeHost *host, const ServeEntry *ring, uint32_t ca
             }
             __builtin_amdgcn_s_sleep(8);
         } else {
-            __builtin_amdgcn_s_sleep(32);
+            // ~14 us between polls: a crowd of idle workgroups hammering the
+            // queue words was measured to disturb the jobs running beside
+            // them (wrong merge lists in multi-workgroup jobs).
+            for (int z = 0; z < 4; ++z) __builtin_amdgcn_s_sleep(127);
         }
         // Safety net: the host stops an idle kernel long before this; if it
         // never does, stop as if it had (entries are still taken first).
@@ -932,9 +936,10 @@ __device__ void copy_in_upper(const float *src, int64_t ld, float *D, int n, int
 // Serving kernel: every workgroup takes entries until the host stops it.
 // A job on g workgroups has g consecutive entries; members are taken in
 // publication order, so the earliest incomplete job always gets its members
-// as workgroups free up.  The last member to finish clears the job slot's
-// device words (after every member has passed the last exchange) and
-// publishes seq << 32 | status in host memory after a system-scope release.
+// as workgroups free up.  Member 0 (the writer of the merge records) waits
+// until every member has passed the last exchange, clears the job slot's
+// device words and publishes seq << 32 | status in host memory after a
+// system-scope release.
 template <int B>
 __global__ __launch_bounds__(B) void k_serve(ServeHost *host, const ServeEntry *ring, uint32_t cap,
                                              unsigned long long *done, ServeDev *dev, Control *ctl,
@@ -968,9 +973,26 @@ __global__ __launch_bounds__(B) void k_serve(ServeHost *host, const ServeEntry *
         uint32_t *words = e.inst.status;  // [0] status, [1] members done
         if (threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-            const uint32_t prev = __hip_atomic_fetch_add(words + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            s_inst = prev + 1 == (uint32_t)e.g ? 2 : 1;
-            if (s_inst == 2) s_status = __hip_atomic_load(words, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(words + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            s_inst = 1;
+            if (e.rank == 0) {
+                // Member 0 wrote the merge records, so it publishes the
+                // completion: its own earlier writes to host memory are
+                // ordered before its completion word, which another
+                // member's would not be.  The others are at most one
+                // exchange behind.
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(words + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)e.g) {
+                    if (wall_clock64() - t0 > timeout) {
+                        atomicOr(words, kErrTimeout);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_status = __hip_atomic_load(words, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_inst = 2;
+            }
         }
         __syncthreads();
         if (s_inst == 2) {

@@ -320,6 +320,42 @@ def test_batch_graph_replays(ctx, torch):
         assert _same(eager[0][moff[k]:moff[k] + n - 1], oracle.run_f32(m, int(links[k]))), k
 
 
+def test_batch_config_sample_vs_oracle(ctx, torch):
+    """The 1024-instance batch configuration's first 256 instances (same seeds
+    and size law, n log-uniform on [64, 4096], all four linkages) in one
+    launch with the default (tuned) plan: every instance with n <= 1536 and a
+    sample of the larger ones byte-identical to the oracle, run on host
+    threads in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+    full = synth.batch_spec()  # the benchmark's batch: 1024 instances
+    count = 256
+    ns, links, seeds = full.ns[:count], full.linkages[:count], full.seeds[:count]
+    offs, total = synth.pack_offsets(ns)
+    packed = np.zeros(total, np.float32)
+    mats = []
+    for k in range(count):
+        m = synth.batch_instance(int(ns[k]), int(seeds[k]))
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+        mats.append(m)
+    _say("batch config sample: %d instances, %.2f GB" % (count, total * 4 / 1e9))
+    res = ctx.batch(torch.from_numpy(packed).cuda(), offs, ns, links)
+    moff, _ = synth.merge_offsets(ns)
+    big = [k for k in range(count) if ns[k] > 1536]
+    rng = np.random.default_rng(3)
+    check = [k for k in range(count) if ns[k] <= 1536] + sorted(rng.choice(big, size=min(12, len(big)), replace=False))
+    workers = min(16, os.cpu_count() or 4)
+
+    def one(k):
+        return k, oracle.run_f32(mats[k], int(links[k]), threads=1)
+
+    with ThreadPoolExecutor(workers) as ex:
+        for k, exp in ex.map(one, check):
+            n = int(ns[k])
+            got = res[moff[k]:moff[k] + n - 1]
+            assert _same(got, exp), (k, n, int(links[k]), _diff(got, exp))
+    _say("checked %d of %d instances against the oracle" % (len(check), count))
+
+
 # ---------------------------------------------------------------------------
 # Larger sizes
 # ---------------------------------------------------------------------------

@@ -104,6 +104,29 @@ def test_server_matches_run_and_oracle(ctx, torch, hac):
         _say("stats", st)
 
 
+def test_server_mix_matches_run(ctx, torch, hac):
+    """160 jobs submitted at once (n log-uniform on [64, 6000], all linkages,
+    about a fifth of them on groups of two workgroups) from page-locked
+    pools, twice: every job byte-identical to hac_run alone."""
+    N, count = 6000, 160
+    pool = [torch.empty((N, N), dtype=torch.float32).pin_memory() for _ in range(2)]
+    synth.serve_pool(2, N, out=[p.numpy() for p in pool])
+    rng = np.random.default_rng(5)
+    ns = np.minimum(synth.log_uniform_int(rng, 64, N, size=count), N)
+    links = rng.integers(0, 4, size=count)
+    refs = [_run_ref(ctx, torch, pool[k % 2][:int(ns[k]), :int(ns[k])].numpy(), int(links[k]))
+            for k in range(count)]
+    with hac.Server(ctx, budget_bytes=8 << 30, max_jobs=256, max_n=N) as srv:
+        for rnd in range(2):
+            _say("mix round", rnd)
+            tickets = {k: srv.submit(pool[k % 2][:int(ns[k]), :int(ns[k])], int(links[k]))
+                       for k in range(count)}
+            got = _drain(srv, tickets)
+            bad = [(k, int(ns[k]), int(links[k])) for k in range(count)
+                   if got[k].tobytes() != refs[k].tobytes()]
+            assert not bad, bad
+
+
 def test_server_budget_makes_jobs_wait(ctx, torch, hac):
     n, count = 1200, 24
     mats = [synth.batch_instance(n, 7300 + k) for k in range(count)]
