@@ -241,7 +241,8 @@ def serve_leg(torch, hac, ctx, requests, warmup, rate, budget_gb, big_n):
             "requests": requests, "warmup": warmup,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
-            "jobs_per_s": requests / span, "offered_jobs_per_s": rate,
+            "jobs_per_s": requests / span, "nominal_rate_per_s": rate,
+            "offered_jobs_per_s": (requests - 1) / float(tr.arrivals[len(tr.ns) - 1] - tr.arrivals[warmup]),
             "matrix_gb_per_s": mbytes / span / 1e9,
             "alone_vs_mix_identical": bool(same), "alone_vs_mix_sample": len(sample),
             "peak_gb": st["peak_bytes"] / 1e9, "kernel_launches": st["kernel_launches"],

@@ -882,52 +882,31 @@ __device__ __forceinline__ float ld_host(const float *p) {
 }
 
 // Serving: workgroup w of a job's g copies from the job's host matrix
-// (page-locked memory read over the bus; leading dimension ld) the part of
-// the strict upper triangle that it will itself read: the whole upper part
-// of its own rows (its set-up reads them) and, of every other row, the
-// entries in its own columns (its Lance-Williams updates read them).  Every
-// matrix entry a workgroup later reads was thus written by that workgroup
-// (or holds the same input value written by two), so no plain data crosses
-// workgroups, as in the rest of the merge loop.  One wave per row, up to 16
-// loads in flight per lane.
+// (page-locked memory read over the bus; leading dimension ld) the strict
+// upper triangle of the rows it owns, one wave per row with up to 16 loads in
+// flight per lane.  Its set-up reads only these rows; the entries of other
+// rows that its merge loop reads in its own columns are read after the
+// set-up exchange with device-scope loads (multi-workgroup paths).
 template <int B>
 __device__ void copy_in_upper(const float *src, int64_t ld, float *D, int n, int g, int w) {
     constexpr int W = B / 64;
     constexpr int U = 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int own_ch = own_chunks(n, g, w);
     for (int i = wv; i < n - 1; i += W) {
+        if (owner_of_row(i, g) != w) continue;
         const float *sr = src + (size_t)i * (size_t)ld;
         float *dr = D + (size_t)i * (size_t)n;
-        if (owner_of_row(i, g) == w) {
-            for (int c0 = i + 1; c0 < n; c0 += 64 * U) {
-                float v[U];
+        for (int c0 = i + 1; c0 < n; c0 += 64 * U) {
+            float v[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = c0 + lane + 64 * u;
-                    v[u] = c < n ? ld_host(sr + c) : 0.0f;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = c0 + lane + 64 * u;
-                    if (c < n) dr[c] = v[u];
-                }
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + lane + 64 * u;
+                v[u] = c < n ? ld_host(sr + c) : 0.0f;
             }
-        } else {
-            for (int lq0 = 0; lq0 < own_ch; lq0 += U) {
-                float v[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int lq = lq0 + u;
-                    const int c = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-                    v[u] = (c > i && c < n) ? ld_host(sr + c) : 0.0f;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int lq = lq0 + u;
-                    const int c = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-                    if (c > i && c < n) dr[c] = v[u];
-                }
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + lane + 64 * u;
+                if (c < n) dr[c] = v[u];
             }
         }
     }
