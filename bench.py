@@ -29,15 +29,41 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def alg_bytes_run(n, st):
-    """Algorithmic HBM bytes of one hac_run launch:
-    set-up reads the strict upper triangle and writes its mirror (4 bytes
-    each way per off-diagonal pair: 4 n(n-1) bytes); each Lance-Williams
-    update of an entry reads D[i][k], D[j][k] and writes D[i][k], D[k][i]
-    (16 bytes); each rescan reads one fp32 per live entry it visits; each
-    merge writes a 16-byte record."""
-    return (4.0 * n * (n - 1) + 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"]
-            + 16.0 * (n - 1))
+PMC_PROFILE = os.path.join(ROOT, "profiles", "k_run_rmsd_like_n32768_pmc.md")
+ENGINE_SOURCES = [os.path.join(ROOT, "paper_1709_06816_amd", "csrc", f) for f in ("hac_engine.hip", "hac_engine.h")]
+
+
+def alg_bytes_merge_kernel(n, st):
+    """Algorithmic HBM bytes of one launch of the merge kernel k_run: each
+    Lance-Williams update of an entry reads D[i][k], D[j][k] and writes
+    D[i][k], D[k][i] (16 bytes); each rescan reads one fp32 per live entry it
+    visits; each merge writes a 16-byte record."""
+    return 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"] + 16.0 * (n - 1)
+
+
+def alg_bytes_setup(n):
+    """k_setup reads the strict upper triangle and writes its mirror."""
+    return 4.0 * n * (n - 1)
+
+
+def measured_traffic(n):
+    """HBM bytes per k_run launch from the committed counter profile, if it
+    was taken on this input size with the engine sources as they are now."""
+    import hashlib
+    try:
+        line = next(l for l in open(PMC_PROFILE) if l.startswith("pmc-json:"))
+        rec = json.loads(line[len("pmc-json:"):])
+    except (OSError, StopIteration, ValueError):
+        return None, "no counter profile"
+    h = hashlib.sha256()
+    for p in ENGINE_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    if rec.get("engine_sha256") != h.hexdigest():
+        return None, "engine changed since the counters were taken"
+    if "n=%d" % n not in rec.get("workload", ""):
+        return None, "counters were taken at another size"
+    return rec["traffic_bytes"], os.path.relpath(PMC_PROFILE, ROOT)
 
 
 def cpu_baseline(d, link, n, budget_s, gpu_prefix):
@@ -312,7 +338,7 @@ def main():
         step()
         ctx.sync()
     torch.cuda.synchronize()
-    kms, stats = [], None
+    kms, ims, stats = [], [], None
     log("timing %d steps" % args.steps)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -320,13 +346,16 @@ def main():
         ctx.sync()
         stats = ctx.stats()
         kms.append(stats["kernel_ms"])
+        ims.append(stats["init_ms"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = elapsed * 1000.0 / args.steps
     merges = np.frombuffer(out.cpu().numpy().tobytes(), dtype=hac.MERGE_DTYPE)
     kernel_ms = float(np.mean(kms))
-    ab = alg_bytes_run(n, stats)
+    ab = alg_bytes_merge_kernel(n, stats)
     achieved = ab / (kernel_ms / 1000.0) / 1e9
+    traffic, traffic_src = measured_traffic(n)
+    init_ms = float(np.mean(ims))
     log("step %.1f ms, merge kernel %.1f ms, %d workgroups" % (ms_step, kernel_ms, stats["workgroups"]))
 
     result = {
@@ -348,12 +377,17 @@ def main():
         "dendrogram_s": ms_step / 1000.0,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_source": traffic_src,
             "kernel": "k_run (persistent merge kernel)", "kernel_ms": kernel_ms,
             "alg_bytes_per_launch": ab, "workgroups": stats["workgroups"],
             "rescans": stats["rescans"], "rescan_elems": stats["rescan_elems"],
             "update_elems": stats["update_elems"],
-            "note": "latency-bound: one grid-wide exchange per merge",
+            "traffic_gbs": None if traffic is None else traffic / (kernel_ms / 1000.0) / 1e9,
+            "note": "latency-bound: one grid-wide exchange and dependent row loads per merge",
+            "setup_kernel": {"kernel": "k_setup", "ms": init_ms, "alg_bytes": alg_bytes_setup(n),
+                             "achieved_gbs": alg_bytes_setup(n) / (init_ms / 1000.0) / 1e9
+                             if init_ms > 0 else None},
         },
     }
     if not args.no_batch:
