@@ -75,6 +75,11 @@ typedef enum {
 #define HAC_PRESERVE_INPUT (1u << 0) /* work on a library-owned copy; dist is left unchanged */
 #define HAC_OUT_DEVICE     (1u << 1) /* out is device memory; the call returns once the work is
                                         enqueued on the stream, and hac_sync() reports its status */
+#define HAC_MODE_SCAN      (1u << 2) /* hac_run only: no cached row minima; before every merge each
+                                        workgroup scans the live upper part of all its rows, the
+                                        paper's own step (Section 5.3 step 1).  Same merge list,
+                                        O(n^3) bytes instead of O(n^2): a reference for the
+                                        memory-bound design the cache replaces */
 
 /*
  * hac_create -- open a context on HIP device `device` (ordinal).
@@ -95,7 +100,7 @@ int hac_destroy(hac_ctx *ctx);
  *   linkage: a hac_linkage value.
  *   out:     n-1 records in merge order; host memory, or device memory with
  *            HAC_OUT_DEVICE (caller-owned either way).
- *   flags:   HAC_PRESERVE_INPUT | HAC_OUT_DEVICE.
+ *   flags:   HAC_PRESERVE_INPUT | HAC_OUT_DEVICE | HAC_MODE_SCAN.
  *   stream:  hipStream_t to enqueue on; NULL = HIP's default (null) stream.
  *   Without HAC_OUT_DEVICE the call blocks until out is filled and returns
  *   the run's status; on HAC_EINPUT out is left untouched.

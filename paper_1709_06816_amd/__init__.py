@@ -33,6 +33,7 @@ HAC_OK, HAC_EINVAL, HAC_EINPUT, HAC_ENOMEM, HAC_EDEVICE, HAC_ENODEV, HAC_EBUSY, 
     HAC_ETIMEDOUT, HAC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PRESERVE_INPUT = 1
 OUT_DEVICE = 2
+MODE_SCAN = 4
 OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE, OPT_PROFILE, OPT_BLOCK = 1, 2, 3, 4, 5, 6
 OPT_AUTOTUNE, OPT_BATCH_BLOCK, OPT_BATCH_GROUP, OPT_GRAPH = 7, 8, 9, 10
 MAX_N = 65536
@@ -190,7 +191,7 @@ class Context:
         out["phase_max_ms"] = dict(zip(PHASES, list(s.phase_max_ms)))
         return out
 
-    def run(self, dist, linkage, preserve: bool = False, out=None, stream=None) -> np.ndarray:
+    def run(self, dist, linkage, preserve: bool = False, out=None, stream=None, scan: bool = False) -> np.ndarray:
         """Cluster one n x n fp32 device matrix.  Returns MERGE_DTYPE[n-1].
 
         With ``out`` given as a device buffer (torch uint8/int32 tensor of
@@ -204,11 +205,11 @@ class Context:
         import torch
         if dist.dtype != torch.float32:
             raise ValueError("dist must be float32")
-        return self.run_ptr(_dev_ptr(dist), n, linkage, preserve=preserve, out=out, stream=stream)
+        return self.run_ptr(_dev_ptr(dist), n, linkage, preserve=preserve, out=out, stream=stream, scan=scan)
 
-    def run_ptr(self, dist_ptr: int, n: int, linkage, preserve: bool = False, out=None,
+    def run_ptr(self, dist_ptr: int, n: int, linkage, preserve: bool = False, out=None, scan: bool = False,
                 stream=None):
-        flags = PRESERVE_INPUT if preserve else 0
+        flags = (PRESERVE_INPUT if preserve else 0) | (MODE_SCAN if scan else 0)
         s = _stream_of(stream)
         if out is None:
             res = np.zeros(max(n - 1, 0), MERGE_DTYPE)

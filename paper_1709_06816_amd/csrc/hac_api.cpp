@@ -518,7 +518,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     if (!dist) return fail(c, HAC_EINVAL, "dist is NULL");
     if (n < 1 || n > HAC_MAX_N) return fail(c, HAC_EINVAL, "n=%d outside 1..%d", n, HAC_MAX_N);
     if (linkage < 0 || linkage > 3) return fail(c, HAC_EINVAL, "linkage %d is not 0..3", linkage);
-    if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE | HAC_MODE_SCAN)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
     if (n > 1 && !out) return fail(c, HAC_EINVAL, "out is NULL");
     int rc = set_device(c);
     if (rc) return rc;
@@ -539,7 +539,10 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     int g = 1;
     if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1), false) > c->lds_max) {
         // Measured on MI355X: about one workgroup per 512 items, up to 64.
-        int want = c->opt_wgs > 0 ? (int)c->opt_wgs : std::max(2, std::min(64, n / 512));
+        // The paper's scan mode is bandwidth-bound: as many workgroups as fit.
+        int want = c->opt_wgs > 0 ? (int)c->opt_wgs
+                   : (flags & HAC_MODE_SCAN) ? nch
+                                             : std::max(2, std::min(64, n / 512));
         g = std::max(1, std::min(want, nch));
         while (g < nch && hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max) ++g;
         const size_t lds = hac::lds_bytes(n, hac::own_rows(n, g), false);
@@ -589,7 +592,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     inst.n = n;
     inst.link = linkage;
     inst.exchange = (int32_t)c->opt_exchange;
-    inst.flags = c->opt_profile ? hac::kFlagProfile : 0;
+    inst.flags = (c->opt_profile ? hac::kFlagProfile : 0) | ((flags & HAC_MODE_SCAN) ? hac::kFlagScan : 0);
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 
     HIP_TRY(c, hipEventRecord(c->ev[0], s));

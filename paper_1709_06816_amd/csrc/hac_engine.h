@@ -56,7 +56,10 @@ struct Instance {
     int32_t flags;       // kFlag*
 };
 
-enum : int32_t { kFlagProfile = 1 };  // time the phases of the merge loop (costs ~0.5 us per merge)
+enum : int32_t {
+    kFlagProfile = 1,  // time the phases of the merge loop (costs ~0.5 us per merge)
+    kFlagScan = 2,     // no cached row minima: every merge rescans every live row (Section 5.3 step 1)
+};
 
 // Rows a workgroup owns when g workgroups share n items.
 int own_rows(int n, int g);

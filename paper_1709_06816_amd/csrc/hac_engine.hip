@@ -506,7 +506,7 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // (v_k, i) is folded in afterwards with an atomic minimum.  Ties resolve as
 // in the lexicographic order: any other column attaining the old minimum lies
 // to the right of the old partner.
-template <int B>
+template <int B, bool kScan>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
                            uint64_t timeout, Stats &st, uint32_t epoch0, bool coh) {
     constexpr int W = B / 64;
@@ -524,12 +524,14 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     }
     __syncthreads();
     // Merge s uses exchange epoch epoch0 + 1 + s (epochs below epoch0 + 1
-    // were used by the caller).
+    // were used by the caller); in scan mode epochs epoch0 + 1 + 2s (argmin)
+    // and epoch0 + 2 + 2s (the updated matrix is complete).
+    constexpr bool scan = kScan;
     fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(epoch0 + 1) & 1][0]);
     int i_prev = -1;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
-        const uint32_t e = epoch0 + (uint32_t)s + 1u;
+        const uint32_t e = epoch0 + (uint32_t)s * (scan ? 2u : 1u) + 1u;
         const int b = e & 1;
         // The other parity's accumulators were last read before the last
         // barrier of the previous merge; clear them for epoch e+1.
@@ -591,7 +593,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             atomicAnd(&L.amask[j >> 5], ~(1u << (j & 31)));
             if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
         }
-        for (int li = tid; li < own_ch * 64; li += B) {
+        for (int li = tid; li < (scan ? 0 : own_ch * 64); li += B) {
             const int k = row_of_local(li, g, w);
             if (k >= n || k == i || k == j) continue;
             uint64_t c = L.cache[li];
@@ -641,6 +643,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 D[(size_t)k * n + i] = v;
                 st.update_elems++;
                 const uint64_t key = ((uint64_t)ord32(v) << 32) | ((uint64_t)i << 16);
+                if (scan) continue;  // every row is scanned again below
                 if (k > i) q2 = umin64(q2, ((uint64_t)ord32(v) << 32) | ((uint64_t)k << 16));
                 if (k < i)  // the row's new entry at column i (see above)
                     atomicMin(reinterpret_cast<unsigned long long *>(&L.cache[(lq * 64) + lane]),
@@ -658,8 +661,32 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         }
         if (prof) st.lap(kPhCand);
 
-        // ---- local candidates for the next argmin -------------------------
-        fold_candidates<B>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
+        if (scan) {
+            // ---- the paper's step 1 literally: every workgroup scans the
+            // live upper part of all its rows for the next argmin ---------
+            if (tid == 0)
+                for (int q = 0; q < 4; ++q) s_acc[b][q] = s_acc[b ^ 1][q] = kEmpty;
+            __syncthreads();
+            // Every workgroup's updated entries are in place (epoch e+1).
+            if (g > 1 && !group_exchange<B>(I, g, w, e + 1u, ctl, timeout)) return;
+            for (int li = tid; li < own_ch * 64; li += B) {
+                const int k = row_of_local(li, g, w);
+                L.cache[li] = kEmptyRow;
+                if (k < n && is_live(L.amask, k)) L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
+            }
+            __syncthreads();
+            const uint32_t nscan = s_nresc;
+            rescan_rows<B>(D, n, g, w, L, nscan, -1, st.rescan_elems, coh);
+            __syncthreads();
+            if (tid == 0) {
+                st.rescans += nscan;
+                s_nresc = 0;
+            }
+            fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b][0]);
+        } else {
+            // ---- local candidates for the next argmin ---------------------
+            fold_candidates<B>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
+        }
         i_prev = i;
     }
 }
@@ -698,7 +725,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I) {
     if (bad) atomicOr(I.status, kErrInput);
 }
 
-template <int B>
+template <int B, bool kScan>
 __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t timeout) {
     extern __shared__ __align__(16) uint8_t smem[];
     Stats st;
@@ -716,7 +743,7 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
         L.cache[li] = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmptyRow;
     }
     __syncthreads();
-    merge_loop<B>(I, g, w, L, ctl, timeout, st, 0u, false);
+    merge_loop<B, kScan>(I, g, w, L, ctl, timeout, st, 0u, false);
     flush_stats<B>(ctl, st);
 }
 
@@ -759,7 +786,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     }
     init_masks<B>(L, n);  // size1 shares space with the tile
     __syncthreads();
-    merge_loop<B>(I, g, w, L, ctl, timeout, st, epoch0, g > 1);
+    merge_loop<B, false>(I, g, w, L, ctl, timeout, st, epoch0, g > 1);
 }
 
 // Batch: the first `ngroups` entries of `order` are run by fixed groups of
@@ -1018,8 +1045,12 @@ size_t lds_bytes(int n, int own, bool in_kernel_setup) {
 hipError_t engine_setup(size_t max_lds, size_t *usable) {
     // Dynamic LDS may use what the static LDS of the kernels leaves free.
     size_t static_max = 0;
-    const void *fns[] = {reinterpret_cast<const void *>(&k_run<256>), reinterpret_cast<const void *>(&k_run<512>),
-                         reinterpret_cast<const void *>(&k_run<1024>), reinterpret_cast<const void *>(&k_batch<256>),
+    const void *fns[] = {reinterpret_cast<const void *>(&k_run<256, false>),
+                         reinterpret_cast<const void *>(&k_run<512, false>),
+                         reinterpret_cast<const void *>(&k_run<1024, false>),
+                         reinterpret_cast<const void *>(&k_run<256, true>),
+                         reinterpret_cast<const void *>(&k_run<512, true>),
+                         reinterpret_cast<const void *>(&k_run<1024, true>), reinterpret_cast<const void *>(&k_batch<256>),
                          reinterpret_cast<const void *>(&k_batch<1024>), reinterpret_cast<const void *>(&k_serve<256>),
                          reinterpret_cast<const void *>(&k_serve<1024>)};
     for (const void *fn : fns) {
@@ -1037,11 +1068,14 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
     return hipSuccess;
 }
 
-static const void *run_kernel(int block) {
+static const void *run_kernel(int block, bool scan) {
     switch (block) {
-    case 256: return reinterpret_cast<const void *>(&k_run<256>);
-    case 512: return reinterpret_cast<const void *>(&k_run<512>);
-    default: return reinterpret_cast<const void *>(&k_run<1024>);
+    case 256: return scan ? reinterpret_cast<const void *>(&k_run<256, true>)
+                          : reinterpret_cast<const void *>(&k_run<256, false>);
+    case 512: return scan ? reinterpret_cast<const void *>(&k_run<512, true>)
+                          : reinterpret_cast<const void *>(&k_run<512, false>);
+    default: return scan ? reinterpret_cast<const void *>(&k_run<1024, true>)
+                         : reinterpret_cast<const void *>(&k_run<1024, false>);
     }
 }
 
@@ -1052,7 +1086,7 @@ static const void *batch_kernel(int block) {
 
 int engine_occupancy(size_t lds, int block, bool batch) {
     int blocks = 0;
-    const void *fn = batch ? batch_kernel(block) : run_kernel(block);
+    const void *fn = batch ? batch_kernel(block) : run_kernel(block, false);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, block, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -1111,8 +1145,9 @@ hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint
     Control *a1 = ctl;
     uint64_t a2 = timeout_ticks;
     void *args[] = {&a0, &a1, &a2};
-    if (g == 1) return hipLaunchKernel(run_kernel(block), dim3(1), dim3(block), args, lds, stream);
-    return hipLaunchCooperativeKernel(run_kernel(block), dim3(g), dim3(block), args, (unsigned)lds, stream);
+    const bool scan = (inst.flags & kFlagScan) != 0;
+    if (g == 1) return hipLaunchKernel(run_kernel(block, scan), dim3(1), dim3(block), args, lds, stream);
+    return hipLaunchCooperativeKernel(run_kernel(block, scan), dim3(g), dim3(block), args, (unsigned)lds, stream);
 }
 
 hipError_t launch_batch(const BatchLaunch &b, Control *ctl, uint64_t timeout_ticks, hipStream_t stream) {

@@ -186,6 +186,34 @@ def test_n1_and_errors(ctx, torch):
     assert e.value.code == hac.HAC_EINVAL
 
 
+@pytest.mark.parametrize("link", LINKS)
+def test_scan_mode_matches_oracle(ctx, torch, link):
+    """HAC_MODE_SCAN (the paper's full rescan before every merge, Section 5.3
+    step 1) gives the same bytes as the oracle and as the cached path, on
+    one workgroup and on groups of workgroups, including a tie-heavy
+    matrix."""
+    import paper_1709_06816_amd as hac
+    cases = [(synth.batch_instance(300, 301), 0), (synth.batch_instance(1000, 1001), 0),
+             (synth.batch_instance(1000, 1002), 4), (synth.quantized_matrix(700, 703), 8),
+             (synth.batch_instance(2500, 2501), 16)]
+    for d, wgs in cases:
+        n = d.shape[0]
+        _say("scan mode n=%d wgs=%d %s" % (n, wgs, link))
+        if wgs:
+            ctx.set_option(hac.OPT_SINGLE_WG_N, 1)
+            ctx.set_option(hac.OPT_WORKGROUPS, wgs)
+        try:
+            t = torch.from_numpy(np.ascontiguousarray(d)).cuda()
+            got = ctx.run(t, link, preserve=True, scan=True)
+            cached = ctx.run(t, link, preserve=True)
+        finally:
+            ctx.set_option(hac.OPT_SINGLE_WG_N, 0)
+            ctx.set_option(hac.OPT_WORKGROUPS, 0)
+        exp = oracle.run_f32(d, link)
+        assert _same(got, exp), (n, wgs, _diff(got, exp))
+        assert _same(cached, exp), (n, wgs)
+
+
 # ---------------------------------------------------------------------------
 # Batched launch
 # ---------------------------------------------------------------------------
