@@ -409,8 +409,9 @@ def main():
             "alg_bytes_per_launch": ab, "workgroups": stats["workgroups"],
             "rescans": stats["rescans"], "rescan_elems": stats["rescan_elems"],
             "update_elems": stats["update_elems"],
+            "deferred_rescans": bool(stats["deferred"]), "forced_rounds": stats["forced_rounds"],
             "traffic_gbs": None if traffic is None else traffic / (kernel_ms / 1000.0) / 1e9,
-            "note": "latency-bound: one grid-wide exchange and dependent row loads per merge",
+            "note": "latency-bound: one grid-wide exchange per merge; rescans run during the exchange wait",
             "setup_kernel": {"kernel": "k_setup", "ms": init_ms, "alg_bytes": alg_bytes_setup(n),
                              "achieved_gbs": alg_bytes_setup(n) / (init_ms / 1000.0) / 1e9
                              if init_ms > 0 else None},

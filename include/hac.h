@@ -158,6 +158,14 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        (instance count, plan, workspace) and relaunched with
  *                        the new descriptors (1 = on, the default; 0 = plain
  *                        stream launches).  Results are identical either way.
+ *   HAC_OPT_DEFER        hac_run on more than one workgroup: a row whose cached
+ *                        partner merged keeps its old minimum as a lower bound
+ *                        and is rescanned while its workgroup waits for the
+ *                        next argmin, instead of before the next update
+ *                        (1 = on, the default; 0 = rescan at once).  A bound
+ *                        that wins an argmin forces the workgroups to rescan
+ *                        their stale rows and repeat that argmin, so the merge
+ *                        list is the same either way (Section 4 step 1).
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
@@ -169,7 +177,8 @@ typedef enum {
     HAC_OPT_AUTOTUNE = 7,
     HAC_OPT_BATCH_BLOCK = 8,
     HAC_OPT_BATCH_GROUP = 9,
-    HAC_OPT_GRAPH = 10
+    HAC_OPT_GRAPH = 10,
+    HAC_OPT_DEFER = 11
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 
@@ -193,6 +202,9 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *   graph:             hac_batch: 0 = stream launches, 1 = an existing graph was
  *                      relaunched, 2 = a graph was built for this call; with a
  *                      graph kernel_ms covers upload, fills and kernel
+ *   forced_rounds:     hac_run with deferred rescans: extra argmin rounds taken
+ *                      because a row's lower bound won (see HAC_OPT_DEFER)
+ *   deferred:          1 if the last hac_run deferred its rescans
  */
 typedef struct {
     double kernel_ms;
@@ -206,6 +218,9 @@ typedef struct {
     double phase_max_ms[5];
     int32_t group;
     int32_t graph;
+    int64_t forced_rounds;
+    int32_t deferred;
+    int32_t reserved;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

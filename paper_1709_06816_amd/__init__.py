@@ -36,6 +36,7 @@ OUT_DEVICE = 2
 MODE_SCAN = 4
 OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE, OPT_PROFILE, OPT_BLOCK = 1, 2, 3, 4, 5, 6
 OPT_AUTOTUNE, OPT_BATCH_BLOCK, OPT_BATCH_GROUP, OPT_GRAPH = 7, 8, 9, 10
+OPT_DEFER = 11
 MAX_N = 65536
 MAX_BATCH_N = 8192
 
@@ -64,7 +65,8 @@ class _Stats(ctypes.Structure):
                 ("update_elems", ctypes.c_int64), ("workgroups", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("phase_avg_ms", ctypes.c_double * 5),
                 ("phase_max_ms", ctypes.c_double * 5), ("group", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("forced_rounds", ctypes.c_int64),
+                ("deferred", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")

@@ -55,13 +55,14 @@ struct hac_ctx {
     int64_t opt_block = 0, opt_batch_block = 0, opt_batch_group = 0, opt_autotune = 1;
     std::unordered_map<std::string, BatchPlan> plans;  // tuned batch plans by size mix
     int64_t opt_graph = 1;
+    int64_t opt_defer = 1;
     std::unordered_map<std::string, hipGraphExec_t> graphs;  // batch graphs by layout
 
     // State of the last enqueued call, for hac_sync / stats.
     bool pending = false;
     hipStream_t pending_stream = nullptr;
     int pending_count = 0;           // status words to check
-    int pending_wgs = 0, pending_block = 0, pending_group = 0, pending_graph = 0;
+    int pending_wgs = 0, pending_block = 0, pending_group = 0, pending_graph = 0, pending_deferred = 0;
 };
 
 namespace {
@@ -151,9 +152,10 @@ uint64_t timeout_ticks(const hac_ctx *c) {
     return (uint64_t)ms * (uint64_t)(c->wallclock_khz > 0 ? c->wallclock_khz : 100000);
 }
 
-// Workgroups that can be co-resident for a hac_run launch with `lds` bytes.
-int max_coresident(hac_ctx *c, size_t lds, int block) {
-    int per_cu = hac::engine_occupancy(lds, block, false);
+// Workgroups that can be co-resident for a hac_run launch with `lds` bytes
+// (merge kernel variant selected by the kFlag* bits in run_flags).
+int max_coresident(hac_ctx *c, size_t lds, int block, int32_t run_flags) {
+    int per_cu = hac::engine_occupancy(lds, block, false, run_flags);
     if (per_cu < 1) per_cu = 1;
     return per_cu * c->cus;
 }
@@ -171,6 +173,8 @@ int check_status(hac_ctx *c) {
     c->stats.rescans = (int64_t)ctl->rescans;
     c->stats.rescan_elems = (int64_t)ctl->rescan_elems;
     c->stats.update_elems = (int64_t)ctl->update_elems;
+    c->stats.forced_rounds = (int64_t)ctl->forced;
+    c->stats.deferred = c->pending_deferred;
     c->stats.workgroups = c->pending_wgs;
     c->stats.block = c->pending_block;
     c->stats.group = c->pending_group;
@@ -482,6 +486,7 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
         return HAC_OK;
     case HAC_OPT_AUTOTUNE: c->opt_autotune = value != 0; return HAC_OK;
     case HAC_OPT_GRAPH: c->opt_graph = value != 0; return HAC_OK;
+    case HAC_OPT_DEFER: c->opt_defer = value != 0; return HAC_OK;
     case HAC_OPT_BLOCK:
         if (value != 0 && value != 256 && value != 512 && value != 1024)
             return fail(c, HAC_EINVAL, "block size %lld is not 256, 512 or 1024", (long long)value);
@@ -537,7 +542,10 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     const int block = c->opt_block > 0 ? (int)c->opt_block : hac::kRunBlock;
     const int single_n = c->opt_single_n > 0 ? (int)c->opt_single_n : kDefaultSingleWgN;
     int g = 1;
+    // Multi-workgroup runs defer rescans (off with HAC_OPT_DEFER = 0).
+    int32_t run_flags = (c->opt_profile ? hac::kFlagProfile : 0) | ((flags & HAC_MODE_SCAN) ? hac::kFlagScan : 0);
     if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1), false) > c->lds_max) {
+        if (c->opt_defer && !(flags & HAC_MODE_SCAN)) run_flags |= hac::kFlagDefer;
         // Measured on MI355X: about one workgroup per 512 items, up to 64.
         // The paper's scan mode is bandwidth-bound: as many workgroups as fit.
         int want = c->opt_wgs > 0 ? (int)c->opt_wgs
@@ -547,7 +555,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
         while (g < nch && hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max) ++g;
         const size_t lds = hac::lds_bytes(n, hac::own_rows(n, g), false);
         if (lds > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit in LDS", n);
-        const int cap = max_coresident(c, lds, block);
+        const int cap = max_coresident(c, lds, block, run_flags);
         if (g > cap) g = cap;
         if (hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max)
             return fail(c, HAC_EDEVICE, "n=%d needs more co-resident workgroups than the device holds", n);
@@ -592,7 +600,8 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     inst.n = n;
     inst.link = linkage;
     inst.exchange = (int32_t)c->opt_exchange;
-    inst.flags = (c->opt_profile ? hac::kFlagProfile : 0) | ((flags & HAC_MODE_SCAN) ? hac::kFlagScan : 0);
+    if (g == 1) run_flags &= ~hac::kFlagDefer;
+    inst.flags = run_flags;
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
@@ -604,6 +613,8 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     c->pending_wgs = g;
     c->pending_block = block;
     c->pending_group = g;
+    c->pending_graph = 0;
+    c->pending_deferred = (run_flags & hac::kFlagDefer) ? 1 : 0;
     return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags);
 }
 
@@ -704,6 +715,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->pending_block = plan.block;
     c->pending_group = B.group;
     c->pending_graph = graphed;
+    c->pending_deferred = 0;
     return finish(c, s, count, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)rec_extent, flags);
 }
 

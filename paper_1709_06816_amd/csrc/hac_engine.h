@@ -39,6 +39,7 @@ struct Control {
     unsigned long long rescans;
     unsigned long long rescan_elems;
     unsigned long long update_elems;
+    unsigned long long forced;        // extra argmin rounds forced by a row's lower bound (kFlagDefer)
     unsigned long long prof_sum[8];   // per phase, summed over workgroups (wall-clock ticks)
     unsigned long long prof_max[8];   // per phase, largest workgroup total
 };
@@ -59,6 +60,8 @@ struct Instance {
 enum : int32_t {
     kFlagProfile = 1,  // time the phases of the merge loop (costs ~0.5 us per merge)
     kFlagScan = 2,     // no cached row minima: every merge rescans every live row (Section 5.3 step 1)
+    kFlagDefer = 4,    // rows whose partner merged keep a lower bound and are rescanned while
+                       // their workgroup waits in the next exchange (single instance, g > 1)
 };
 
 // Rows a workgroup owns when g workgroups share n items.
@@ -155,8 +158,9 @@ int serve_occupancy(size_t lds, int block);
 // LDS a launch may request.
 hipError_t engine_setup(size_t max_lds, size_t *usable);
 
-// Workgroups of the run (batch = false) or batch kernel with `block` threads
-// that fit on one CU with `lds` bytes of dynamic LDS.
-int engine_occupancy(size_t lds, int block, bool batch);
+// Workgroups of the run (batch = false; the variant `run_flags` (kFlag*)
+// selects) or batch kernel with `block` threads that fit on one CU with `lds`
+// bytes of dynamic LDS.
+int engine_occupancy(size_t lds, int block, bool batch, int32_t run_flags = 0);
 
 }  // namespace hac

@@ -52,6 +52,9 @@ constexpr uint64_t kEmpty = ~0ull;                     // "no candidate"
 constexpr uint32_t kEmptyOrd = 0xFFFFFFFFu;             // above ord(+inf)
 constexpr uint64_t kEmptyRow = 0xFFFFFFFFFFFF0000ull;   // cache entry without partner
 constexpr uint64_t kHi32 = 0xFFFFFFFF00000000ull;
+// Low bit of a row's cache entry: the row's partner merged and the entry
+// holds only a lower bound of its minimum (partner field 0; deferred mode).
+constexpr uint64_t kStale = 1ull;
 constexpr int kMaxWaves = 16;
 // Loads in flight per thread: chunks per wave per update batch, and 16-byte
 // loads per rescan step.  Large workgroups need fewer per thread for the same
@@ -182,6 +185,11 @@ __shared__ uint64_t s_red[2][kMaxWaves];
 __shared__ uint64_t s_acc[2][4];
 __shared__ uint32_t s_nresc;
 __shared__ uint32_t s_fail;
+// Deferred rescans: the smallest key (bound : 32 | row : 16 | 0) over this
+// workgroup's stale rows, reduced with the candidates, and the minimum the
+// rescan of that row during the next exchange accumulates.
+__shared__ uint64_t s_bgkey;
+__shared__ uint64_t s_bgacc;
 __shared__ int s_inst;
 
 // Minimum of (a, b) over the workgroup, returned to every thread.
@@ -272,7 +280,7 @@ __device__ void setup_block(float *D, int n, int R, float *tile, uint32_t &bad, 
 }
 
 struct Stats {
-    unsigned long long rescans = 0, rescan_elems = 0, update_elems = 0;
+    unsigned long long rescans = 0, rescan_elems = 0, update_elems = 0, forced = 0;
     unsigned long long prof[kPhases] = {0, 0, 0, 0, 0};  // thread 0 only
     uint64_t mark = 0;
     // Charge the time since the last mark to phase p (thread 0).
@@ -325,11 +333,15 @@ __device__ bool get_slot(const uint64_t *s, uint64_t gen, uint64_t &p1, uint64_t
 // Publish this workgroup's candidates of epoch e (s_acc[e&1][0..1]), wait for
 // the rest of the group, and leave the group-wide minima in s_acc[e&1][2..3]
 // (Section 5.3 steps 2-4: every processor ends up with the same global
-// minimum).  Ends with a barrier.  Returns false if the wait was abandoned;
-// the decision is the same for every thread.
-template <int B>
+// minimum).  Waves other than wave 0 run `bg()` meanwhile (whole waves; it
+// must not touch s_acc).  Ends with a barrier.  Returns false if the wait was
+// abandoned; the decision is the same for every thread.
+struct NoBg {
+    __device__ void operator()() const {}
+};
+template <int B, class Bg = NoBg>
 __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Control *ctl,
-                               uint64_t timeout) {
+                               uint64_t timeout, Bg bg = Bg()) {
     const int b = e & 1;
     const uint64_t gen = e & 0xFFFFu;
     uint64_t *base = I.slots + (size_t)b * (g + 1) * kSlotStride;
@@ -356,6 +368,8 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             lds_min(&s_acc[b][2], m1);
             lds_min(&s_acc[b][3], m2);
+        } else {
+            bg();
         }
         __syncthreads();
         if (I.exchange == kExchReducer && threadIdx.x == 0 && !s_fail) {
@@ -369,6 +383,8 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_acc[b][2] = m1;
             s_acc[b][3] = m2;
+        } else if (threadIdx.x >= 64) {
+            bg();
         }
         __syncthreads();
     }
@@ -404,90 +420,109 @@ __device__ void init_masks(const Lds &L, int n) {
     for (int k = threadIdx.x; k < n; k += B) L.size1[k] = 0;
 }
 
+// Minimum (D[k][l], l) over live l > k, l != skip, of row k, folded into the
+// LDS word *acc: the row tail is cut into segments of one wave's loads, and
+// waves WV0 .. B/64-1 take segments round-robin starting at wave
+// (WV0 + base) mod their number (so consecutive rows start on different
+// waves).  Returns the number of segments.  Waves below WV0 only count.
+template <int B, int WV0>
+__device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_t *amask, int skip, int base,
+                        uint64_t *acc, unsigned long long &elems, bool coh) {
+    constexpr int W = B / 64 - WV0, U = seg_unroll<B>();
+    static_assert(W >= 1, "no wave left to rescan");
+    const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6) - WV0;
+    const float *row = D + (size_t)k * n;
+    const int first_sg = ((wv - base) % W + W) % W;
+    int nseg;
+    if ((n & 3) == 0) {
+        // 16-byte loads over quads q0 .. n/4-1; row starts are aligned.
+        const int q0 = (k + 1) >> 2, nq = n >> 2;
+        nseg = (nq - q0 + 64 * U - 1) / (64 * U);
+        if (wv < 0) return nseg;
+        for (int sg = first_sg; sg < nseg; sg += W) {
+            float4 x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + sg * 64 * U + u * 64 + lane;
+                x[u] = q < nq ? ld_f32x4(row + 4 * q, coh) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+            uint64_t best = kEmpty;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + sg * 64 * U + u * 64 + lane;
+                if (q >= nq) continue;
+                uint32_t m = (amask[q >> 3] >> ((q & 7) * 4)) & 0xFu;  // live l = 4q..4q+3
+                const int below = k + 1 - 4 * q;                         // those with l <= k
+                if (below > 0) m &= (0xFu << below) & 0xFu;
+                if ((skip >> 2) == q) m &= ~(1u << (skip & 3));
+                elems += __popc(m);
+                const float v[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if ((m >> c) & 1u)
+                        best = umin64(best, ((uint64_t)ord32(v[c]) << 32) | ((uint64_t)(4 * q + c) << 16));
+            }
+            lds_min(acc, best);
+        }
+    } else {
+        const int l0 = k + 1;
+        nseg = (n - l0 + 64 * U - 1) / (64 * U);
+        if (wv < 0) return nseg;
+        for (int sg = first_sg; sg < nseg; sg += W) {
+            float x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int l = l0 + sg * 64 * U + u * 64 + lane;
+                x[u] = l < n ? ld_f32(row + l, coh) : 0.0f;
+            }
+            uint64_t best = kEmpty;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int l = l0 + sg * 64 * U + u * 64 + lane;
+                if (l < n && l != skip && is_live(amask, l)) {
+                    best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
+                    ++elems;
+                }
+            }
+            lds_min(acc, best);
+        }
+    }
+    return nseg;
+}
+
 // Rescan the rows queued in rlist (their entries were reset to kEmptyRow when
 // queued): each entry becomes the smallest (D[k][l], l) over live l > k with
-// l != skip.  Row tails are cut into segments of one wave's loads; the waves
-// take segments round-robin across all queued rows and fold their lanes'
-// minima into the entry with LDS atomics, so no barrier is needed per row.
+// l != skip.  All waves take segments round-robin across all queued rows and
+// fold their lanes' minima into the entry with LDS atomics, so no barrier is
+// needed per row.
 template <int B>
 __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, const Lds &L,
                             uint32_t nresc, int skip, unsigned long long &elems, bool coh) {
-    constexpr int W = B / 64, U = seg_unroll<B>();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int base = 0;
     for (uint32_t r = 0; r < nresc; ++r) {
         const int li = L.rlist[r];
-        const int k = row_of_local(li, g, w);
-        const float *row = D + (size_t)k * n;
-        const int first_sg = ((wv - base) % W + W) % W;
-        int nseg;
-        if ((n & 3) == 0) {
-            // 16-byte loads over quads q0 .. n/4-1; row starts are aligned.
-            const int q0 = (k + 1) >> 2, nq = n >> 2;
-            nseg = (nq - q0 + 64 * U - 1) / (64 * U);
-            for (int sg = first_sg; sg < nseg; sg += W) {
-                float4 x[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int q = q0 + sg * 64 * U + u * 64 + lane;
-                    x[u] = q < nq ? ld_f32x4(row + 4 * q, coh) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                }
-                uint64_t best = kEmpty;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int q = q0 + sg * 64 * U + u * 64 + lane;
-                    if (q >= nq) continue;
-                    uint32_t m = (L.amask[q >> 3] >> ((q & 7) * 4)) & 0xFu;  // live l = 4q..4q+3
-                    const int below = k + 1 - 4 * q;                           // those with l <= k
-                    if (below > 0) m &= (0xFu << below) & 0xFu;
-                    if ((skip >> 2) == q) m &= ~(1u << (skip & 3));
-                    elems += __popc(m);
-                    const float v[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        if ((m >> c) & 1u)
-                            best = umin64(best, ((uint64_t)ord32(v[c]) << 32) | ((uint64_t)(4 * q + c) << 16));
-                }
-                lds_min(&L.cache[li], best);
-            }
-        } else {
-            const int l0 = k + 1;
-            nseg = (n - l0 + 64 * U - 1) / (64 * U);
-            for (int sg = first_sg; sg < nseg; sg += W) {
-                float x[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int l = l0 + sg * 64 * U + u * 64 + lane;
-                    x[u] = l < n ? ld_f32(row + l, coh) : 0.0f;
-                }
-                uint64_t best = kEmpty;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int l = l0 + sg * 64 * U + u * 64 + lane;
-                    if (l < n && l != skip && is_live(L.amask, l)) {
-                        best = umin64(best, ((uint64_t)ord32(x[u]) << 32) | ((uint64_t)l << 16));
-                        ++elems;
-                    }
-                }
-                lds_min(&L.cache[li], best);
-            }
-        }
-        base += nseg;
+        base += scan_row<B, 0>(D, n, row_of_local(li, g, w), L.amask, skip, base, &L.cache[li], elems, coh);
     }
 }
 
 // Fold the smallest cached key (ord:32 | row:16 | partner:16) of this
-// workgroup's live rows other than `skip` into *acc.
-template <int B>
+// workgroup's live rows other than `skip` into *acc.  A stale row's key is
+// (bound, row, 0), below every key the row can really have.  With kBg the
+// smallest stale key is also folded into s_bgkey.
+template <int B, bool kBg = false>
 __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, int skip, uint64_t *acc) {
-    uint64_t p = kEmpty;
+    uint64_t p = kEmpty, q = kEmpty;
     for (int li = threadIdx.x; li < own_ch * 64; li += B) {
         const int k = row_of_local(li, g, w);
         const uint64_t c = L.cache[li];
-        if (k < n && k != skip && (uint32_t)(c >> 32) != kEmptyOrd)
-            p = umin64(p, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
+        if (k < n && k != skip && (uint32_t)(c >> 32) != kEmptyOrd) {
+            const uint64_t key = (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull);
+            p = umin64(p, key);
+            if (kBg && (c & kStale)) q = umin64(q, key);
+        }
     }
     lds_min(acc, p);
+    if (kBg) lds_min(&s_bgkey, q);
 }
 
 // All n-1 merges of one instance on workgroup w of a group of g.  On entry
@@ -501,16 +536,33 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 //   * i < k < j: the row loses column j; if its partner was j its minimum is
 //     recomputed over l != j (column i lies to its left).
 //   * k > j: unchanged.
-// Rows whose partner was i or j are therefore rescanned over l not in {i, j}
-// right after the argmin, overlapping the loads of rows i and j, and the new
-// (v_k, i) is folded in afterwards with an atomic minimum.  Ties resolve as
-// in the lexicographic order: any other column attaining the old minimum lies
-// to the right of the old partner.
-template <int B, bool kScan>
+// kLoopCached rescans rows whose partner was i or j right after the argmin,
+// overlapping the loads of rows i and j, and folds the new (v_k, i) in
+// afterwards with an atomic minimum.  Ties resolve as in the lexicographic
+// order: any other column attaining the old minimum lies to the right of the
+// old partner.
+//
+// kLoopDefer (g > 1) takes those rescans off the merge's critical path: such a
+// row becomes stale, keeping its old minimum as a lower bound (lowered by
+// every new entry it receives, so it stays a bound whatever the linkage), and
+// offers (bound, k, 0) to the argmin, a key below any the row can really
+// have.  Each workgroup rescans its stale row of smallest key while its wave 0
+// waits in the next exchange; nobody writes that row then (it is neither the
+// merged row nor written by another workgroup outside merges of it), so the
+// result is its exact minimum at the state the argmin is taken in.  When a
+// stale key wins the argmin anyway, every workgroup rescans all its stale rows
+// and the argmin is repeated (an extra exchange).
+//
+// kLoopScan drops the cache: before every argmin every workgroup rescans all
+// its live rows, as Section 5.3 step 1 scans the whole matrix.
+enum : int { kLoopCached = 0, kLoopDefer = 1, kLoopScan = 2 };
+
+template <int B, int kMode>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
                            uint64_t timeout, Stats &st, uint32_t epoch0, bool coh) {
     constexpr int W = B / 64;
     constexpr int U = upd_batch<B>();
+    constexpr bool scan = kMode == kLoopScan, defer = kMode == kLoopDefer;
     const int n = I.n, link = I.link;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
     const int own_ch = own_chunks(n, g, w);
@@ -521,39 +573,96 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         for (int b = 0; b < 2; ++b)
             for (int q = 0; q < 4; ++q) s_acc[b][q] = kEmpty;
         s_nresc = 0;
+        s_bgkey = kEmpty;
+        s_bgacc = kEmptyRow;
     }
     __syncthreads();
-    // Merge s uses exchange epoch epoch0 + 1 + s (epochs below epoch0 + 1
-    // were used by the caller); in scan mode epochs epoch0 + 1 + 2s (argmin)
-    // and epoch0 + 2 + 2s (the updated matrix is complete).
-    constexpr bool scan = kScan;
-    fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(epoch0 + 1) & 1][0]);
+    // Exchange epochs after epoch0 (used by the caller) are taken one by one:
+    // one per merge, one more for each forced round (deferred mode) and for
+    // the second exchange of every merge (scan mode).
+    uint32_t e = epoch0;
+    fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(e + 1) & 1][0]);
     int i_prev = -1;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
-        const uint32_t e = epoch0 + (uint32_t)s * (scan ? 2u : 1u) + 1u;
-        const int b = e & 1;
+        ++e;
+        int b = e & 1;
         // The other parity's accumulators were last read before the last
         // barrier of the previous merge; clear them for epoch e+1.
         if (tid == 0)
             for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;
         __syncthreads();
-        uint64_t p1, p2;
-        if (g > 1) {
+        // Deferred mode: the stale row of smallest key (from the last fold) is
+        // rescanned into s_bgacc during the exchange; its cache entry keeps
+        // the bound until the result is taken over below.
+        int li_bg = -1;
+        if (defer) {
+            const uint64_t bk = s_bgkey;
+            const int k_bg = (int)((bk >> 16) & 0xFFFFull);
+            if (bk != kEmpty) li_bg = local_of_row(k_bg, g);
+            auto bg = [&]() {
+                if (li_bg >= 0) scan_row<B, 1>(D, n, k_bg, L.amask, -1, 0, &s_bgacc, st.rescan_elems, coh);
+            };
+            if (g > 1) {
+                if (!group_exchange<B>(I, g, w, e, ctl, timeout, bg)) return;
+            } else {
+                if (tid >= 64) bg();
+                __syncthreads();
+            }
+            if (tid == 0) {
+                st.rescans += li_bg >= 0;
+                s_bgkey = kEmpty;  // every thread has read it; the next fold is barriers away
+            }
+        } else if (g > 1) {
             if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
-            p1 = s_acc[b][2];
-            p2 = s_acc[b][3];
-        } else {
-            p1 = s_acc[b][0];
-            p2 = s_acc[b][1];
         }
+        const uint64_t p1 = g > 1 ? s_acc[b][2] : s_acc[b][0];
+        const uint64_t p2 = g > 1 ? s_acc[b][3] : s_acc[b][1];
         if (prof) st.lap(s == 0 ? kPhSetup : kPhWait);
         // Row i_prev's new cache entry: its smallest new value to the right.
         const uint64_t ip_entry = ((uint32_t)(p2 >> 32) != kEmptyOrd) ? p2 : kEmptyRow;
         uint64_t key_ip = kEmpty;
         if (i_prev >= 0 && (uint32_t)(p2 >> 32) != kEmptyOrd)
             key_ip = (p2 & kHi32) | ((uint64_t)i_prev << 16) | ((p2 >> 16) & 0xFFFFull);
-        const uint64_t win = umin64(p1, key_ip);
+        uint64_t win = umin64(p1, key_ip);
+        // A stale row's bound won (partner field 0; a real partner is > 0):
+        // settle every stale row and take the argmin again.
+        while (defer && (uint32_t)(win >> 32) != kEmptyOrd && (win & 0xFFFFull) == 0) {
+            __syncthreads();  // p1, p2 are read; s_nresc is 0
+            if (tid == 0 && i_prev >= 0 && owner_of_row(i_prev, g) == w) L.cache[local_of_row(i_prev, g)] = ip_entry;
+            for (int li = tid; li < own_ch * 64; li += B) {
+                const int k = row_of_local(li, g, w);
+                if (li == li_bg) {
+                    L.cache[li] = s_bgacc;  // already rescanned
+                    continue;
+                }
+                if (k < n && k != i_prev && (L.cache[li] & kStale)) {
+                    L.cache[li] = kEmptyRow;
+                    L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
+                }
+            }
+            __syncthreads();
+            const uint32_t nf = s_nresc;
+            if (nf) rescan_rows<B>(D, n, g, w, L, nf, -1, st.rescan_elems, coh);
+            __syncthreads();
+            if (tid == 0) {
+                st.rescans += nf;
+                st.forced += w == 0;
+                s_nresc = 0;
+                for (int q = 0; q < 4; ++q) s_acc[b][q] = kEmpty;  // for the epoch after the next
+            }
+            // s_acc[b ^ 1] has stayed clear since the top of this merge.
+            ++e;
+            b = e & 1;
+            fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b][0]);
+            __syncthreads();
+            if (g > 1) {
+                if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+                win = s_acc[b][2];
+            } else {
+                win = s_acc[b][0];
+            }
+        }
         if ((uint32_t)(win >> 32) == kEmptyOrd) {
             if (tid == 0) {
                 atomicOr(&ctl->error, kErrInternal);
@@ -601,15 +710,24 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 c = ip_entry;
                 L.cache[li] = c;
             }
+            if (defer && li == li_bg) {
+                c = s_bgacc;  // the row's exact minimum before this merge
+                L.cache[li] = c;
+            }
+            if (defer && (c & kStale)) continue;  // stays a bound
             const int nn = (int)((c >> 16) & 0xFFFFull);
             if ((uint32_t)(c >> 32) != kEmptyOrd && (nn == i || nn == j)) {
-                L.cache[li] = kEmptyRow;  // rebuilt by the rescan below
-                L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
+                if (defer) {
+                    L.cache[li] = (c & kHi32) | kStale;
+                } else {
+                    L.cache[li] = kEmptyRow;  // rebuilt by the rescan below
+                    L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
+                }
             }
         }
         __syncthreads();
         if (prof) st.lap(kPhUpdate);
-        const uint32_t nresc = s_nresc;
+        const uint32_t nresc = defer ? 0u : s_nresc;
         if (nresc) rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems, coh);
         if (prof) st.lap(kPhRescan);
 
@@ -639,15 +757,32 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 if (k >= n || k == i || k == j || !is_live(L.amask, k)) continue;
                 const int nk = link == HAC_WARD ? (int)L.size1[k] + 1 : 1;
                 const float v = lw_update(link, a[u], bv[u], h, ni, nj, nk, ai, aj);
-                Di[k] = v;
-                D[(size_t)k * n + i] = v;
+                if (defer) {
+                    // Written through to the device's point of coherence, so
+                    // that the release before the next exchange has little to
+                    // write back while rescans run beside it (measured).
+                    __hip_atomic_store(reinterpret_cast<uint32_t *>(Di + k), __float_as_uint(v), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(reinterpret_cast<uint32_t *>(D + (size_t)k * n + i), __float_as_uint(v),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    Di[k] = v;
+                    D[(size_t)k * n + i] = v;
+                }
                 st.update_elems++;
                 const uint64_t key = ((uint64_t)ord32(v) << 32) | ((uint64_t)i << 16);
                 if (scan) continue;  // every row is scanned again below
                 if (k > i) q2 = umin64(q2, ((uint64_t)ord32(v) << 32) | ((uint64_t)k << 16));
-                if (k < i)  // the row's new entry at column i (see above)
-                    atomicMin(reinterpret_cast<unsigned long long *>(&L.cache[(lq * 64) + lane]),
-                              (unsigned long long)key);
+                if (k < i) {  // the row's new entry at column i (see above)
+                    uint64_t *ce = &L.cache[(lq * 64) + lane];
+                    if (defer) {
+                        // This lane is the only one touching the entry now.
+                        const uint64_t c = *ce;
+                        *ce = umin64(c, (c & kStale) ? (((uint64_t)ord32(v) << 32) | kStale) : key);
+                    } else {
+                        atomicMin(reinterpret_cast<unsigned long long *>(ce), (unsigned long long)key);
+                    }
+                }
             }
         }
         lds_min(&s_acc[b ^ 1][1], q2);  // row i's candidates for epoch e+1
@@ -658,6 +793,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             L.size1[i] = (uint16_t)(ni + nj - 1);
             st.rescans += nresc;
             s_nresc = 0;
+            s_bgacc = kEmptyRow;  // read by the classification above
         }
         if (prof) st.lap(kPhCand);
 
@@ -668,7 +804,9 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 for (int q = 0; q < 4; ++q) s_acc[b][q] = s_acc[b ^ 1][q] = kEmpty;
             __syncthreads();
             // Every workgroup's updated entries are in place (epoch e+1).
-            if (g > 1 && !group_exchange<B>(I, g, w, e + 1u, ctl, timeout)) return;
+            ++e;
+            b = e & 1;
+            if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout)) return;
             for (int li = tid; li < own_ch * 64; li += B) {
                 const int k = row_of_local(li, g, w);
                 L.cache[li] = kEmptyRow;
@@ -682,10 +820,10 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 st.rescans += nscan;
                 s_nresc = 0;
             }
-            fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b][0]);
+            fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b ^ 1][0]);
         } else {
             // ---- local candidates for the next argmin ---------------------
-            fold_candidates<B>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
+            fold_candidates<B, defer>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
         }
         i_prev = i;
     }
@@ -700,6 +838,7 @@ __device__ void flush_stats(Control *ctl, Stats &st) {
         atomicAdd(&ctl->rescans, a);
         atomicAdd(&ctl->rescan_elems, b);
         atomicAdd(&ctl->update_elems, c);
+        if (st.forced) atomicAdd(&ctl->forced, st.forced);
         for (int p = 0; p < kPhases; ++p) {
             atomicAdd(&ctl->prof_sum[p], st.prof[p]);
             atomicMax(&ctl->prof_max[p], st.prof[p]);
@@ -725,7 +864,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I) {
     if (bad) atomicOr(I.status, kErrInput);
 }
 
-template <int B, bool kScan>
+template <int B, int kMode>
 __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t timeout) {
     extern __shared__ __align__(16) uint8_t smem[];
     Stats st;
@@ -743,7 +882,7 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
         L.cache[li] = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmptyRow;
     }
     __syncthreads();
-    merge_loop<B, kScan>(I, g, w, L, ctl, timeout, st, 0u, false);
+    merge_loop<B, kMode>(I, g, w, L, ctl, timeout, st, 0u, false);
     flush_stats<B>(ctl, st);
 }
 
@@ -786,7 +925,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     }
     init_masks<B>(L, n);  // size1 shares space with the tile
     __syncthreads();
-    merge_loop<B, false>(I, g, w, L, ctl, timeout, st, epoch0, g > 1);
+    merge_loop<B, kLoopCached>(I, g, w, L, ctl, timeout, st, epoch0, g > 1);
 }
 
 // Batch: the first `ngroups` entries of `order` are run by fixed groups of
@@ -1042,15 +1181,31 @@ size_t lds_bytes(int n, int own, bool in_kernel_setup) {
     return (size_t)own * 8 + (size_t)own * 2 + mask + (size1 > tile ? size1 : tile);
 }
 
+template <int B>
+static const void *run_kernel_b(int mode) {
+    switch (mode) {
+    case kLoopDefer: return reinterpret_cast<const void *>(&k_run<B, kLoopDefer>);
+    case kLoopScan: return reinterpret_cast<const void *>(&k_run<B, kLoopScan>);
+    default: return reinterpret_cast<const void *>(&k_run<B, kLoopCached>);
+    }
+}
+
+static const void *run_kernel(int block, int mode) {
+    switch (block) {
+    case 256: return run_kernel_b<256>(mode);
+    case 512: return run_kernel_b<512>(mode);
+    default: return run_kernel_b<1024>(mode);
+    }
+}
+
 hipError_t engine_setup(size_t max_lds, size_t *usable) {
     // Dynamic LDS may use what the static LDS of the kernels leaves free.
     size_t static_max = 0;
-    const void *fns[] = {reinterpret_cast<const void *>(&k_run<256, false>),
-                         reinterpret_cast<const void *>(&k_run<512, false>),
-                         reinterpret_cast<const void *>(&k_run<1024, false>),
-                         reinterpret_cast<const void *>(&k_run<256, true>),
-                         reinterpret_cast<const void *>(&k_run<512, true>),
-                         reinterpret_cast<const void *>(&k_run<1024, true>), reinterpret_cast<const void *>(&k_batch<256>),
+    const void *fns[] = {run_kernel(256, kLoopCached),   run_kernel(512, kLoopCached),
+                         run_kernel(1024, kLoopCached),  run_kernel(256, kLoopDefer),
+                         run_kernel(512, kLoopDefer),    run_kernel(1024, kLoopDefer),
+                         run_kernel(256, kLoopScan),     run_kernel(512, kLoopScan),
+                         run_kernel(1024, kLoopScan),    reinterpret_cast<const void *>(&k_batch<256>),
                          reinterpret_cast<const void *>(&k_batch<1024>), reinterpret_cast<const void *>(&k_serve<256>),
                          reinterpret_cast<const void *>(&k_serve<1024>)};
     for (const void *fn : fns) {
@@ -1068,25 +1223,16 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
     return hipSuccess;
 }
 
-static const void *run_kernel(int block, bool scan) {
-    switch (block) {
-    case 256: return scan ? reinterpret_cast<const void *>(&k_run<256, true>)
-                          : reinterpret_cast<const void *>(&k_run<256, false>);
-    case 512: return scan ? reinterpret_cast<const void *>(&k_run<512, true>)
-                          : reinterpret_cast<const void *>(&k_run<512, false>);
-    default: return scan ? reinterpret_cast<const void *>(&k_run<1024, true>)
-                         : reinterpret_cast<const void *>(&k_run<1024, false>);
-    }
-}
 
 static const void *batch_kernel(int block) {
     return block == 1024 ? reinterpret_cast<const void *>(&k_batch<1024>)
                          : reinterpret_cast<const void *>(&k_batch<256>);
 }
 
-int engine_occupancy(size_t lds, int block, bool batch) {
+int engine_occupancy(size_t lds, int block, bool batch, int32_t run_flags) {
     int blocks = 0;
-    const void *fn = batch ? batch_kernel(block) : run_kernel(block, false);
+    const int mode = (run_flags & kFlagScan) ? kLoopScan : (run_flags & kFlagDefer) ? kLoopDefer : kLoopCached;
+    const void *fn = batch ? batch_kernel(block) : run_kernel(block, mode);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, block, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -1145,9 +1291,9 @@ hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint
     Control *a1 = ctl;
     uint64_t a2 = timeout_ticks;
     void *args[] = {&a0, &a1, &a2};
-    const bool scan = (inst.flags & kFlagScan) != 0;
-    if (g == 1) return hipLaunchKernel(run_kernel(block, scan), dim3(1), dim3(block), args, lds, stream);
-    return hipLaunchCooperativeKernel(run_kernel(block, scan), dim3(g), dim3(block), args, (unsigned)lds, stream);
+    const int mode = (inst.flags & kFlagScan) ? kLoopScan : (inst.flags & kFlagDefer) ? kLoopDefer : kLoopCached;
+    if (g == 1) return hipLaunchKernel(run_kernel(block, mode), dim3(1), dim3(block), args, lds, stream);
+    return hipLaunchCooperativeKernel(run_kernel(block, mode), dim3(g), dim3(block), args, (unsigned)lds, stream);
 }
 
 hipError_t launch_batch(const BatchLaunch &b, Control *ctl, uint64_t timeout_ticks, hipStream_t stream) {

@@ -72,3 +72,30 @@ def test_to_linkage_matrix_matches_scipy():
     assert np.array_equal(z[:, :2], ref[:, :2])
     assert np.allclose(z[:, 2], ref[:, 2], rtol=1e-12)
     assert np.array_equal(z[:, 3], ref[:, 3])
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets the C
+    compiler gives the structures of include/hac.h."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = {"hac_stats": hac._Stats, "hac_server_stats": hac._ServerStats}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", "#include \"hac.h\"", "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, stdout=subprocess.PIPE, text=True).stdout.split("\n")
+    got = dict((" ".join(l.split()[:2]), int(l.split()[2])) for l in out if l.strip())
+    for cname, cls in structs.items():
+        assert got[cname + " size"] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got["%s %s" % (cname, f)] == getattr(cls, f).offset, (cname, f)

@@ -214,6 +214,44 @@ def test_scan_mode_matches_oracle(ctx, torch, link):
         assert _same(cached, exp), (n, wgs)
 
 
+@pytest.mark.parametrize("link", LINKS)
+def test_deferred_rescans_match_oracle(ctx, torch, link):
+    """Multi-workgroup hac_run with rescans deferred into the exchange wait
+    (the default) and with immediate rescans (HAC_OPT_DEFER = 0) give the
+    oracle's bytes.  The tie-heavy quantised matrix makes stale lower
+    bounds win argmins, so the forced extra rounds run too."""
+    import paper_1709_06816_amd as hac
+    cases = [(synth.batch_instance(1000, 1001), 7), (synth.quantized_matrix(700, 703), 8),
+             (synth.rmsd_like(seed=77, n=700), 9), (synth.quantized_matrix(1500, 1507, levels=4), 24),
+             (synth.batch_instance(2500, 2501), 40)]
+    forced = {}
+    for d, wgs in cases:
+        n = d.shape[0]
+        exp = oracle.run_f32(d, link)
+        t = torch.from_numpy(np.ascontiguousarray(d)).cuda()
+        ctx.set_option(hac.OPT_SINGLE_WG_N, 1)
+        ctx.set_option(hac.OPT_WORKGROUPS, wgs)
+        try:
+            for defer in (1, 0):
+                _say("deferred rescans n=%d wgs=%d %s defer=%d" % (n, wgs, link, defer))
+                ctx.set_option(hac.OPT_DEFER, defer)
+                got = ctx.run(t, link, preserve=True)
+                st = ctx.stats()
+                assert st["deferred"] == defer and st["workgroups"] == wgs
+                assert _same(got, exp), (n, wgs, defer, _diff(got, exp))
+                if defer:
+                    forced[n] = st["forced_rounds"]
+                else:
+                    assert st["forced_rounds"] == 0
+        finally:
+            ctx.set_option(hac.OPT_DEFER, 1)
+            ctx.set_option(hac.OPT_SINGLE_WG_N, 0)
+            ctx.set_option(hac.OPT_WORKGROUPS, 0)
+    _say("forced rounds %s: %r" % (link, forced))
+    if link == "complete":
+        assert forced[700] > 0
+
+
 # ---------------------------------------------------------------------------
 # Batched launch
 # ---------------------------------------------------------------------------
