@@ -189,7 +189,7 @@ __shared__ uint32_t s_fail;
 // workgroup's stale rows, reduced with the candidates, and the minimum the
 // rescan of that row during the next exchange accumulates.
 __shared__ uint64_t s_bgkey;
-__shared__ uint64_t s_bgacc;
+__shared__ uint64_t s_bgacc[2];
 __shared__ int s_inst;
 
 // Minimum of (a, b) over the workgroup, returned to every thread.
@@ -421,14 +421,14 @@ __device__ void init_masks(const Lds &L, int n) {
 }
 
 // Minimum (D[k][l], l) over live l > k, l != skip, of row k, folded into the
-// LDS word *acc: the row tail is cut into segments of one wave's loads, and
-// waves WV0 .. B/64-1 take segments round-robin starting at wave
-// (WV0 + base) mod their number (so consecutive rows start on different
+// LDS word *acc: the row tail is cut into segments of one wave's loads (U
+// per lane), and waves WV0 .. B/64-1 take segments round-robin starting at
+// wave (WV0 + base) mod their number (so consecutive rows start on different
 // waves).  Returns the number of segments.  Waves below WV0 only count.
-template <int B, int WV0>
+template <int B, int WV0, int U = seg_unroll<B>()>
 __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_t *amask, int skip, int base,
                         uint64_t *acc, unsigned long long &elems, bool coh) {
-    constexpr int W = B / 64 - WV0, U = seg_unroll<B>();
+    constexpr int W = B / 64 - WV0;
     static_assert(W >= 1, "no wave left to rescan");
     const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6) - WV0;
     const float *row = D + (size_t)k * n;
@@ -506,23 +506,19 @@ __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, co
 }
 
 // Fold the smallest cached key (ord:32 | row:16 | partner:16) of this
-// workgroup's live rows other than `skip` into *acc.  A stale row's key is
-// (bound, row, 0), below every key the row can really have.  With kBg the
-// smallest stale key is also folded into s_bgkey.
-template <int B, bool kBg = false>
+// workgroup's live rows other than `skip` into *acc, using threads 0 .. NT-1
+// (whole waves).  A stale row's key is (bound, row, 0), below every key the
+// row can really have.
+template <int NT>
 __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, int skip, uint64_t *acc) {
-    uint64_t p = kEmpty, q = kEmpty;
-    for (int li = threadIdx.x; li < own_ch * 64; li += B) {
+    uint64_t p = kEmpty;
+    for (int li = threadIdx.x; li < own_ch * 64; li += NT) {
         const int k = row_of_local(li, g, w);
         const uint64_t c = L.cache[li];
-        if (k < n && k != skip && (uint32_t)(c >> 32) != kEmptyOrd) {
-            const uint64_t key = (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull);
-            p = umin64(p, key);
-            if (kBg && (c & kStale)) q = umin64(q, key);
-        }
+        if (k < n && k != skip && (uint32_t)(c >> 32) != kEmptyOrd)
+            p = umin64(p, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
     }
     lds_min(acc, p);
-    if (kBg) lds_min(&s_bgkey, q);
 }
 
 // All n-1 merges of one instance on workgroup w of a group of g.  On entry
@@ -546,12 +542,15 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // row becomes stale, keeping its old minimum as a lower bound (lowered by
 // every new entry it receives, so it stays a bound whatever the linkage), and
 // offers (bound, k, 0) to the argmin, a key below any the row can really
-// have.  Each workgroup rescans its stale row of smallest key while its wave 0
-// waits in the next exchange; nobody writes that row then (it is neither the
-// merged row nor written by another workgroup outside merges of it), so the
-// result is its exact minimum at the state the argmin is taken in.  When a
-// stale key wins the argmin anyway, every workgroup rescans all its stale rows
-// and the argmin is repeated (an extra exchange).
+// have.  After each update every workgroup rescans its stale row of smallest
+// key (chosen while classifying) over l != i, with waves 1.. while wave 0
+// folds the candidates, publishes them and waits in the exchange; the update
+// has already folded the row's new (v_k, i) into the same accumulator.
+// Nobody else writes that row meanwhile (it is neither the merged row nor
+// written by another workgroup outside merges of it), so the result is its
+// exact minimum after this merge, taken over when the next merge classifies.
+// When a stale key wins an argmin anyway, every workgroup rescans all its
+// stale rows and the argmin is repeated (an extra exchange).
 //
 // kLoopScan drops the cache: before every argmin every workgroup rescans all
 // its live rows, as Section 5.3 step 1 scans the whole matrix.
@@ -574,7 +573,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             for (int q = 0; q < 4; ++q) s_acc[b][q] = kEmpty;
         s_nresc = 0;
         s_bgkey = kEmpty;
-        s_bgacc = kEmptyRow;
+        s_bgacc[0] = s_bgacc[1] = kEmptyRow;
     }
     __syncthreads();
     // Exchange epochs after epoch0 (used by the caller) are taken one by one:
@@ -582,26 +581,22 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     // the second exchange of every merge (scan mode).
     uint32_t e = epoch0;
     fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(e + 1) & 1][0]);
+    if (defer) __syncthreads();  // later folds and publishes are wave 0's alone
+    // Deferred mode: the stale row rescanned during the coming exchange
+    // (local index, row, column skipped) and its accumulator s_bgacc[s & 1].
+    int li_bg = -1, k_bg = 0, skip_bg = -1;
     int i_prev = -1;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
         ++e;
         int b = e & 1;
-        // The other parity's accumulators were last read before the last
-        // barrier of the previous merge; clear them for epoch e+1.
-        if (tid == 0)
-            for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;
-        __syncthreads();
-        // Deferred mode: the stale row of smallest key (from the last fold) is
-        // rescanned into s_bgacc during the exchange; its cache entry keeps
-        // the bound until the result is taken over below.
-        int li_bg = -1;
+        uint64_t *bgacc = &s_bgacc[(s + 1) & 1];  // the row chosen by the last merge
         if (defer) {
-            const uint64_t bk = s_bgkey;
-            const int k_bg = (int)((bk >> 16) & 0xFFFFull);
-            if (bk != kEmpty) li_bg = local_of_row(k_bg, g);
+            // This workgroup's candidates (wave 0) and the last update are
+            // complete; s_acc[b ^ 1] is cleared below, after the exchange.
             auto bg = [&]() {
-                if (li_bg >= 0) scan_row<B, 1>(D, n, k_bg, L.amask, -1, 0, &s_bgacc, st.rescan_elems, coh);
+                if (li_bg < 0) return;
+                scan_row<B, 1>(D, n, k_bg, L.amask, skip_bg, 0, bgacc, st.rescan_elems, coh);
             };
             if (g > 1) {
                 if (!group_exchange<B>(I, g, w, e, ctl, timeout, bg)) return;
@@ -611,10 +606,15 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             }
             if (tid == 0) {
                 st.rescans += li_bg >= 0;
-                s_bgkey = kEmpty;  // every thread has read it; the next fold is barriers away
+                for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;  // for epoch e+1
             }
-        } else if (g > 1) {
-            if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+        } else {
+            // The other parity's accumulators were last read before the last
+            // barrier of the previous merge; clear them for epoch e+1.
+            if (tid == 0)
+                for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;
+            __syncthreads();
+            if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout)) return;
         }
         const uint64_t p1 = g > 1 ? s_acc[b][2] : s_acc[b][0];
         const uint64_t p2 = g > 1 ? s_acc[b][3] : s_acc[b][1];
@@ -628,12 +628,12 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         // A stale row's bound won (partner field 0; a real partner is > 0):
         // settle every stale row and take the argmin again.
         while (defer && (uint32_t)(win >> 32) != kEmptyOrd && (win & 0xFFFFull) == 0) {
-            __syncthreads();  // p1, p2 are read; s_nresc is 0
+            __syncthreads();  // p1, p2 are read; s_acc[b ^ 1] is clear; s_nresc is 0
             if (tid == 0 && i_prev >= 0 && owner_of_row(i_prev, g) == w) L.cache[local_of_row(i_prev, g)] = ip_entry;
             for (int li = tid; li < own_ch * 64; li += B) {
                 const int k = row_of_local(li, g, w);
                 if (li == li_bg) {
-                    L.cache[li] = s_bgacc;  // already rescanned
+                    L.cache[li] = *bgacc;  // already rescanned
                     continue;
                 }
                 if (k < n && k != i_prev && (L.cache[li] & kStale)) {
@@ -651,7 +651,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 s_nresc = 0;
                 for (int q = 0; q < 4; ++q) s_acc[b][q] = kEmpty;  // for the epoch after the next
             }
-            // s_acc[b ^ 1] has stayed clear since the top of this merge.
+            // s_acc[b ^ 1] has stayed clear since the exchange above.
             ++e;
             b = e & 1;
             fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b][0]);
@@ -702,6 +702,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             atomicAnd(&L.amask[j >> 5], ~(1u << (j & 31)));
             if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
         }
+        uint64_t stale_min = kEmpty;  // deferred mode: smallest stale key
         for (int li = tid; li < (scan ? 0 : own_ch * 64); li += B) {
             const int k = row_of_local(li, g, w);
             if (k >= n || k == i || k == j) continue;
@@ -710,26 +711,40 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 c = ip_entry;
                 L.cache[li] = c;
             }
-            if (defer && li == li_bg) {
-                c = s_bgacc;  // the row's exact minimum before this merge
-                L.cache[li] = c;
+            if (defer) {
+                if (li == li_bg) {
+                    c = *bgacc;  // the row's exact minimum after the last merge
+                    L.cache[li] = c;
+                }
+                const int nn = (int)((c >> 16) & 0xFFFFull);
+                if (!(c & kStale) && (uint32_t)(c >> 32) != kEmptyOrd && (nn == i || nn == j)) {
+                    c = (c & kHi32) | kStale;  // keeps its old minimum as a bound
+                    L.cache[li] = c;
+                }
+                if (c & kStale) stale_min = umin64(stale_min, (c & kHi32) | ((uint64_t)k << 16));
+                continue;
             }
-            if (defer && (c & kStale)) continue;  // stays a bound
             const int nn = (int)((c >> 16) & 0xFFFFull);
             if ((uint32_t)(c >> 32) != kEmptyOrd && (nn == i || nn == j)) {
-                if (defer) {
-                    L.cache[li] = (c & kHi32) | kStale;
-                } else {
-                    L.cache[li] = kEmptyRow;  // rebuilt by the rescan below
-                    L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
-                }
+                L.cache[li] = kEmptyRow;  // rebuilt by the rescan below
+                L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
             }
         }
+        if (defer) lds_min(&s_bgkey, stale_min);
         __syncthreads();
         if (prof) st.lap(kPhUpdate);
         const uint32_t nresc = defer ? 0u : s_nresc;
         if (nresc) rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems, coh);
         if (prof) st.lap(kPhRescan);
+        // The stale row rescanned during the next exchange.
+        int li_nx = -1, k_nx = -1;
+        if (defer) {
+            const uint64_t bk = s_bgkey;
+            if (bk != kEmpty) {
+                k_nx = (int)((bk >> 16) & 0xFFFFull);
+                li_nx = local_of_row(k_nx, g);
+            }
+        }
 
         // ---- Lance-Williams update of row/column i (Section 4 step 3) -----
         float ai = 0.0f, aj = 0.0f;
@@ -779,6 +794,9 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                         // This lane is the only one touching the entry now.
                         const uint64_t c = *ce;
                         *ce = umin64(c, (c & kStale) ? (((uint64_t)ord32(v) << 32) | kStale) : key);
+                        // The rescan of the chosen row skips column i: its
+                        // new entry goes into the accumulator here.
+                        if (k == k_nx) s_bgacc[s & 1] = umin64(s_bgacc[s & 1], key);
                     } else {
                         atomicMin(reinterpret_cast<unsigned long long *>(ce), (unsigned long long)key);
                     }
@@ -793,7 +811,10 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             L.size1[i] = (uint16_t)(ni + nj - 1);
             st.rescans += nresc;
             s_nresc = 0;
-            s_bgacc = kEmptyRow;  // read by the classification above
+            if (defer) {
+                *bgacc = kEmptyRow;  // taken over by the classification above
+                s_bgkey = kEmpty;    // read by every thread before the update
+            }
         }
         if (prof) st.lap(kPhCand);
 
@@ -821,9 +842,16 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 s_nresc = 0;
             }
             fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b ^ 1][0]);
+        } else if (defer) {
+            // ---- wave 0: local candidates for the next argmin; the next
+            // exchange publishes them without a barrier -------------------
+            if (tid < 64) fold_candidates<64>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
+            li_bg = li_nx;
+            k_bg = k_nx;
+            skip_bg = i;
         } else {
             // ---- local candidates for the next argmin ---------------------
-            fold_candidates<B, defer>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
+            fold_candidates<B>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
         }
         i_prev = i;
     }
