@@ -161,11 +161,13 @@ const char *hac_last_error(const hac_ctx *ctx);
  *   HAC_OPT_DEFER        hac_run on more than one workgroup: a row whose cached
  *                        partner merged keeps its old minimum as a lower bound
  *                        and is rescanned while its workgroup waits for the
- *                        next argmin, instead of before the next update
- *                        (1 = on, the default; 0 = rescan at once).  A bound
- *                        that wins an argmin forces the workgroups to rescan
- *                        their stale rows and repeat that argmin, so the merge
- *                        list is the same either way (Section 4 step 1).
+ *                        next argmin, instead of before the next update.
+ *                        0 = never, 1 = with 8 or more workgroups (the
+ *                        default; fewer gain nothing), 2 = with any number.  A
+ *                        bound that wins an argmin forces the workgroups to
+ *                        rescan their stale rows and repeat that argmin, so
+ *                        the merge list is the same either way (Section 4
+ *                        step 1).
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,

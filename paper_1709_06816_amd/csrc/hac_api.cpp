@@ -19,6 +19,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultSingleWgN = 1536;
+constexpr int kDeferMinGroup = 8;       // HAC_OPT_DEFER = 1: defer from this many workgroups on
 constexpr int64_t kDefaultTimeoutMs = 10000;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -486,7 +487,10 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
         return HAC_OK;
     case HAC_OPT_AUTOTUNE: c->opt_autotune = value != 0; return HAC_OK;
     case HAC_OPT_GRAPH: c->opt_graph = value != 0; return HAC_OK;
-    case HAC_OPT_DEFER: c->opt_defer = value != 0; return HAC_OK;
+    case HAC_OPT_DEFER:
+        if (value > 2) return fail(c, HAC_EINVAL, "defer mode %lld is not 0, 1 or 2", (long long)value);
+        c->opt_defer = value;
+        return HAC_OK;
     case HAC_OPT_BLOCK:
         if (value != 0 && value != 256 && value != 512 && value != 1024)
             return fail(c, HAC_EINVAL, "block size %lld is not 256, 512 or 1024", (long long)value);
@@ -542,9 +546,10 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     const int block = c->opt_block > 0 ? (int)c->opt_block : hac::kRunBlock;
     const int single_n = c->opt_single_n > 0 ? (int)c->opt_single_n : kDefaultSingleWgN;
     int g = 1;
-    // Multi-workgroup runs defer rescans (off with HAC_OPT_DEFER = 0).
     int32_t run_flags = (c->opt_profile ? hac::kFlagProfile : 0) | ((flags & HAC_MODE_SCAN) ? hac::kFlagScan : 0);
     if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1), false) > c->lds_max) {
+        // Co-residency is checked for the deferred variant too, which may
+        // be chosen below once g is known.
         if (c->opt_defer && !(flags & HAC_MODE_SCAN)) run_flags |= hac::kFlagDefer;
         // Measured on MI355X: about one workgroup per 512 items, up to 64.
         // The paper's scan mode is bandwidth-bound: as many workgroups as fit.
@@ -600,7 +605,10 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     inst.n = n;
     inst.link = linkage;
     inst.exchange = (int32_t)c->opt_exchange;
-    if (g == 1) run_flags &= ~hac::kFlagDefer;
+    // Deferred rescans pay from about 8 workgroups on (measured at n = 2048 …
+    // 32768); on fewer, each workgroup's stale rows outrun one background
+    // rescan per merge and forced rounds pile up.
+    if (g == 1 || (c->opt_defer == 1 && g < kDeferMinGroup)) run_flags &= ~hac::kFlagDefer;
     inst.flags = run_flags;
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 

@@ -43,10 +43,13 @@ def ctx(torch):
     c.close()
 
 
+_OPTS = {"workgroups": ("OPT_WORKGROUPS", 0), "single_wg_n": ("OPT_SINGLE_WG_N", 0), "defer": ("OPT_DEFER", 1)}
+
+
 def _gpu_run(ctx, torch, d, link, **opts):
     import paper_1709_06816_amd as hac
     for k, v in opts.items():
-        ctx.set_option({"workgroups": hac.OPT_WORKGROUPS, "single_wg_n": hac.OPT_SINGLE_WG_N}[k], v)
+        ctx.set_option(getattr(hac, _OPTS[k][0]), v)
     try:
         t = torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda()
         res = ctx.run(t, link)
@@ -54,7 +57,7 @@ def _gpu_run(ctx, torch, d, link, **opts):
         return res
     finally:
         for k in opts:
-            ctx.set_option({"workgroups": hac.OPT_WORKGROUPS, "single_wg_n": hac.OPT_SINGLE_WG_N}[k], 0)
+            ctx.set_option(getattr(hac, _OPTS[k][0]), _OPTS[k][1])
 
 
 def _same(a, b):
@@ -85,12 +88,15 @@ def test_edge_sizes_single_wg(ctx, torch, n, link):
     assert _same(got, exp), _diff(got, exp)
 
 
+@pytest.mark.parametrize("defer", [1, 2])
 @pytest.mark.parametrize("link", LINKS)
 @pytest.mark.parametrize("n,wgs", [(65, 2), (129, 3), (300, 5), (1000, 7), (1000, 16), (2500, 40)])
-def test_edge_sizes_multi_wg(ctx, torch, n, wgs, link):
+def test_edge_sizes_multi_wg(ctx, torch, n, wgs, link, defer):
+    """Groups of workgroups; defer = 1 (automatic: deferred rescans from 8
+    workgroups on) and 2 (deferred on any group)."""
     d = synth.mixture_8192(seed=2000 + n, n=n)
-    _say("edge multi-wg n=%d wgs=%d %s" % (n, wgs, link))
-    got = _gpu_run(ctx, torch, d, link, single_wg_n=1, workgroups=wgs)
+    _say("edge multi-wg n=%d wgs=%d %s defer=%d" % (n, wgs, link, defer))
+    got = _gpu_run(ctx, torch, d, link, single_wg_n=1, workgroups=wgs, defer=defer)
     exp = oracle.run_f32(d, link)
     assert _same(got, exp), _diff(got, exp)
 
@@ -217,9 +223,10 @@ def test_scan_mode_matches_oracle(ctx, torch, link):
 @pytest.mark.parametrize("link", LINKS)
 def test_deferred_rescans_match_oracle(ctx, torch, link):
     """Multi-workgroup hac_run with rescans deferred into the exchange wait
-    (the default) and with immediate rescans (HAC_OPT_DEFER = 0) give the
-    oracle's bytes.  The tie-heavy quantised matrix makes stale lower
-    bounds win argmins, so the forced extra rounds run too."""
+    (forced on with HAC_OPT_DEFER = 2, also below 8 workgroups), automatic
+    (the default) and immediate (HAC_OPT_DEFER = 0) give the oracle's bytes.
+    The tie-heavy quantised matrix makes stale lower bounds win argmins, so
+    the forced extra rounds run too."""
     import paper_1709_06816_amd as hac
     cases = [(synth.batch_instance(1000, 1001), 7), (synth.quantized_matrix(700, 703), 8),
              (synth.rmsd_like(seed=77, n=700), 9), (synth.quantized_matrix(1500, 1507, levels=4), 24),
@@ -232,16 +239,17 @@ def test_deferred_rescans_match_oracle(ctx, torch, link):
         ctx.set_option(hac.OPT_SINGLE_WG_N, 1)
         ctx.set_option(hac.OPT_WORKGROUPS, wgs)
         try:
-            for defer in (1, 0):
+            for defer in (2, 1, 0):
                 _say("deferred rescans n=%d wgs=%d %s defer=%d" % (n, wgs, link, defer))
                 ctx.set_option(hac.OPT_DEFER, defer)
                 got = ctx.run(t, link, preserve=True)
                 st = ctx.stats()
-                assert st["deferred"] == defer and st["workgroups"] == wgs
+                assert st["workgroups"] == wgs
+                assert st["deferred"] == (defer == 2 or (defer == 1 and wgs >= 8))
                 assert _same(got, exp), (n, wgs, defer, _diff(got, exp))
-                if defer:
+                if defer == 2:
                     forced[n] = st["forced_rounds"]
-                else:
+                elif not st["deferred"]:
                     assert st["forced_rounds"] == 0
         finally:
             ctx.set_option(hac.OPT_DEFER, 1)
