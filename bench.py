@@ -145,6 +145,13 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
         torch.cuda.synchronize()
         tb.append(time.perf_counter() - t0)
         kb.append(ctx.stats()["kernel_ms"])
+    st = ctx.stats()
+    # Algorithmic bytes of the batch kernel: every instance's set-up (read its
+    # strict upper triangle, write the mirror) plus its merge loops, counted
+    # as for the single-instance kernel.
+    ns64 = spec.ns.astype(np.float64)
+    alg = float(np.sum(4.0 * ns64 * (ns64 - 1.0))) + 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"] \
+        + 16.0 * float(mtot)
     log("batch: per-instance loop")
     one_loop()
     torch.cuda.synchronize()
@@ -165,6 +172,11 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
         "speedup_vs_loop": tl / tbm,
         "identical_to_loop": same,
         "merges": int(mtot),
+        "alg_bytes": alg,
+        "achieved_gbs": alg / (float(np.median(kb)) / 1000.0) / 1e9,
+        "frac_hbm_peak": alg / (float(np.median(kb)) / 1000.0) / 1e9 / HBM_PEAK_GBS,
+        "plan": {"block": st["block"], "group": st["group"], "workgroups": st["workgroups"],
+                 "graph": st["graph"]},
     }
 
 

@@ -754,6 +754,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             aj = (float)((double)nj / sum);
         }
         uint64_t q2 = kEmpty;
+        uint64_t pc = kEmpty;  // deferred mode: this workgroup's candidates for epoch e+1
         for (int lq0 = wv; lq0 < own_ch; lq0 += W * U) {
             if (lq0 != wv) {
 #pragma unroll
@@ -788,22 +789,29 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 const uint64_t key = ((uint64_t)ord32(v) << 32) | ((uint64_t)i << 16);
                 if (scan) continue;  // every row is scanned again below
                 if (k > i) q2 = umin64(q2, ((uint64_t)ord32(v) << 32) | ((uint64_t)k << 16));
-                if (k < i) {  // the row's new entry at column i (see above)
+                if (defer) {
+                    // This lane is the only one touching the row's entry now;
+                    // it also folds the final entry into the candidates, so
+                    // no separate pass over the cache is needed.
                     uint64_t *ce = &L.cache[(lq * 64) + lane];
-                    if (defer) {
-                        // This lane is the only one touching the entry now.
-                        const uint64_t c = *ce;
-                        *ce = umin64(c, (c & kStale) ? (((uint64_t)ord32(v) << 32) | kStale) : key);
+                    uint64_t c = *ce;
+                    if (k < i) {  // the row's new entry at column i (see above)
+                        c = umin64(c, (c & kStale) ? (((uint64_t)ord32(v) << 32) | kStale) : key);
+                        *ce = c;
                         // The rescan of the chosen row skips column i: its
                         // new entry goes into the accumulator here.
                         if (k == k_nx) s_bgacc[s & 1] = umin64(s_bgacc[s & 1], key);
-                    } else {
-                        atomicMin(reinterpret_cast<unsigned long long *>(ce), (unsigned long long)key);
                     }
+                    if ((uint32_t)(c >> 32) != kEmptyOrd)
+                        pc = umin64(pc, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
+                } else if (k < i) {  // the row's new entry at column i (see above)
+                    atomicMin(reinterpret_cast<unsigned long long *>(&L.cache[(lq * 64) + lane]),
+                              (unsigned long long)key);
                 }
             }
         }
         lds_min(&s_acc[b ^ 1][1], q2);  // row i's candidates for epoch e+1
+        if (defer) lds_min(&s_acc[b ^ 1][0], pc);
         __syncthreads();
         // Cluster i grows; every thread has read size1[i] and size1[j] for
         // this merge, and nothing reads them again before the next one.
@@ -843,9 +851,8 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             }
             fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b ^ 1][0]);
         } else if (defer) {
-            // ---- wave 0: local candidates for the next argmin; the next
-            // exchange publishes them without a barrier -------------------
-            if (tid < 64) fold_candidates<64>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
+            // The local candidates for the next argmin were folded during the
+            // update; the next exchange publishes them at once.
             li_bg = li_nx;
             k_bg = k_nx;
             skip_bg = i;
