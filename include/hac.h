@@ -231,11 +231,14 @@ int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
  * clustering jobs (each the computation described above) share one GPU.
  *
  * A server owns an HBM arena of hbm_budget_bytes and a persistent kernel on
- * its own streams.  Jobs are admitted in arrival order as soon as the arena
- * holds their matrix and workspace; their matrix is copied host-to-device
- * on a copy stream, then published to the running kernel, whose workgroups
- * take jobs as they free up, so jobs that arrive while others run overlap
- * with them on the device.  Jobs with n above 2048 run on a group of
+ * its own stream.  Jobs are admitted in arrival order as soon as the arena
+ * holds their matrix and workspace, and are then published to the running
+ * kernel, whose workgroups take jobs as they free up, so jobs that arrive
+ * while others run overlap with them on the device.  The kernel reads each
+ * job's matrix straight from host memory over the bus: page-locked memory in
+ * place, pageable memory from a page-locked staging copy that the server's
+ * host thread makes at admission.  Merge records come back the same way, into
+ * page-locked memory of the server.  Jobs with n above 2048 run on a group of
  * workgroups.  A job's merge list is byte-identical to hac_run on the same
  * matrix, whatever else runs beside it.  A host thread of the server drives
  * admission, publication and completion; the kernel stops after a short
