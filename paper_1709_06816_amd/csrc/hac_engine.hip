@@ -581,7 +581,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     // the second exchange of every merge (scan mode).
     uint32_t e = epoch0;
     fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(e + 1) & 1][0]);
-    if (defer) __syncthreads();  // later folds and publishes are wave 0's alone
+    __syncthreads();  // later candidates are folded inside the update loop
     // Deferred mode: the stale row rescanned during the coming exchange
     // (local index, row, column skipped) and its accumulator s_bgacc[s & 1].
     int li_bg = -1, k_bg = 0, skip_bg = -1;
@@ -608,13 +608,24 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 st.rescans += li_bg >= 0;
                 for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;  // for epoch e+1
             }
-        } else {
+        } else if (scan) {
             // The other parity's accumulators were last read before the last
             // barrier of the previous merge; clear them for epoch e+1.
             if (tid == 0)
                 for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;
             __syncthreads();
             if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+        } else {
+            // The candidates were folded during the last update.  Alone, a
+            // workgroup still needs a barrier here: thread 0's size update of
+            // the last merge is read below.
+            if (g > 1) {
+                if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+            } else {
+                __syncthreads();
+            }
+            if (tid == 0)
+                for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;  // for epoch e+1
         }
         const uint64_t p1 = g > 1 ? s_acc[b][2] : s_acc[b][0];
         const uint64_t p2 = g > 1 ? s_acc[b][3] : s_acc[b][1];
@@ -734,7 +745,10 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         __syncthreads();
         if (prof) st.lap(kPhUpdate);
         const uint32_t nresc = defer ? 0u : s_nresc;
-        if (nresc) rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems, coh);
+        if (nresc) {
+            rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems, coh);
+            if (!scan) __syncthreads();  // rescanned entries are final before the update folds them
+        }
         if (prof) st.lap(kPhRescan);
         // The stale row rescanned during the next exchange.
         int li_nx = -1, k_nx = -1;
@@ -754,7 +768,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             aj = (float)((double)nj / sum);
         }
         uint64_t q2 = kEmpty;
-        uint64_t pc = kEmpty;  // deferred mode: this workgroup's candidates for epoch e+1
+        uint64_t pc = kEmpty;  // this workgroup's candidates for epoch e+1
         for (int lq0 = wv; lq0 < own_ch; lq0 += W * U) {
             if (lq0 != wv) {
 #pragma unroll
@@ -804,14 +818,21 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                     }
                     if ((uint32_t)(c >> 32) != kEmptyOrd)
                         pc = umin64(pc, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
-                } else if (k < i) {  // the row's new entry at column i (see above)
-                    atomicMin(reinterpret_cast<unsigned long long *>(&L.cache[(lq * 64) + lane]),
-                              (unsigned long long)key);
+                } else {
+                    uint64_t *ce = &L.cache[(lq * 64) + lane];
+                    uint64_t c;
+                    if (k < i)  // the row's new entry at column i (see above)
+                        c = umin64(atomicMin(reinterpret_cast<unsigned long long *>(ce), (unsigned long long)key),
+                                   key);
+                    else
+                        c = *ce;
+                    if ((uint32_t)(c >> 32) != kEmptyOrd)
+                        pc = umin64(pc, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
                 }
             }
         }
         lds_min(&s_acc[b ^ 1][1], q2);  // row i's candidates for epoch e+1
-        if (defer) lds_min(&s_acc[b ^ 1][0], pc);
+        if (!scan) lds_min(&s_acc[b ^ 1][0], pc);
         __syncthreads();
         // Cluster i grows; every thread has read size1[i] and size1[j] for
         // this merge, and nothing reads them again before the next one.
@@ -856,9 +877,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             li_bg = li_nx;
             k_bg = k_nx;
             skip_bg = i;
-        } else {
-            // ---- local candidates for the next argmin ---------------------
-            fold_candidates<B>(L, n, g, w, own_ch, i, &s_acc[b ^ 1][0]);
         }
         i_prev = i;
     }
