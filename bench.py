@@ -41,9 +41,11 @@ def alg_bytes_merge_kernel(n, st):
     return 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"] + 16.0 * (n - 1)
 
 
-def alg_bytes_setup(n):
-    """k_setup reads the strict upper triangle and writes its mirror."""
-    return 4.0 * n * (n - 1)
+def alg_bytes_setup(n, preserve=True):
+    """k_setup reads the strict upper triangle and writes its mirror; when the
+    input is preserved it also writes the upper triangle into the library's
+    working copy (no separate copy kernel)."""
+    return (6.0 if preserve else 4.0) * n * (n - 1)
 
 
 def measured_traffic(n):

@@ -578,12 +578,13 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     rc = ensure_pinned(c, ctl_bytes + kAlign);
     if (rc) return rc;
 
+    // With HAC_PRESERVE_INPUT the set-up kernel reads the caller's matrix and
+    // writes both triangles of the library's working copy (no separate copy).
     float *D = dist;
     if (flags & HAC_PRESERVE_INPUT) {
         const size_t bytes = (size_t)n * n * 4;
         rc = ensure_dev(c, reinterpret_cast<void **>(&c->dcopy), &c->dcopy_cap, bytes, "input copy");
         if (rc) return rc;
-        HIP_TRY(c, hipMemcpyAsync(c->dcopy, dist, bytes, hipMemcpyDeviceToDevice, s));
         D = c->dcopy;
     }
     hac_merge *dev_out = out;
@@ -615,7 +616,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
     if (sl_bytes) HIP_TRY(c, hac::launch_zero(ws + sl_off, sl_bytes / 4, s));
-    hipError_t e = hac::launch_run(inst, g, block, ctl, timeout_ticks(c), s, c->ev[1]);
+    hipError_t e = hac::launch_run(inst, dist, g, block, ctl, timeout_ticks(c), s, c->ev[1]);
     if (e != hipSuccess) return hip_fail(c, e, "merge kernel launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     c->pending_wgs = g;

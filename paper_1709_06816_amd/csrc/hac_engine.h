@@ -75,9 +75,11 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream);
 
 // Single instance: set-up kernel over the whole device, then the merge kernel
 // on g workgroups (g > 1 uses a cooperative launch so that all are
-// co-resident).  `setup_done` is recorded on the stream between the two.
-hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint64_t timeout_ticks,
-                      hipStream_t stream, hipEvent_t setup_done);
+// co-resident).  The set-up reads the strict upper triangle from `src` and
+// writes both triangles of inst.D (src == inst.D: in place).  `setup_done`
+// is recorded on the stream between the two.
+hipError_t launch_run(const Instance &inst, const float *src, int g, int block, Control *ctl,
+                      uint64_t timeout_ticks, hipStream_t stream, hipEvent_t setup_done);
 
 // A batch launch: `count` instances in the order of `order` (device
 // int32[count], largest first); the first `ngroups` of them run on fixed

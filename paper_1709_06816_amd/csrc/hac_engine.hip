@@ -230,12 +230,14 @@ __device__ unsigned long long block_sum(unsigned long long v) {
 
 // Set-up of row block R (rows 64R .. 64R+63), playing the part of the
 // paper's initial distribution of the matrix: for every tile (R, C >= R)
-// validate and canonicalise the strict-upper entries, mirror them into tile
-// (C, R), and keep each row's running minimum.  Hands the minimum key
-// (ord : 32 | column : 16) of row 64R + r to `sink(r, key)` (lane 0 of the
-// wave holding that row; kEmpty if the row has no entry to its right).
+// read the strict-upper entries from src, validate and canonicalise them,
+// store them in D (when D is not src, or to canonicalise -0), mirror them
+// into tile (C, R) of D, and keep each row's running minimum.  Hands the
+// minimum key (ord : 32 | column : 16) of row 64R + r to `sink(r, key)`
+// (lane 0 of the wave holding that row; kEmpty if the row has no entry to
+// its right).  The diagonal of D is never written (nor read later).
 template <int B, class Sink>
-__device__ void setup_block(float *D, int n, int R, float *tile, uint32_t &bad, Sink sink) {
+__device__ void setup_block(const float *src, float *D, int n, int R, float *tile, uint32_t &bad, Sink sink) {
     constexpr int W = B / 64, P = 64 / W;  // rows of a tile per wave
     const int T = (n + 63) >> 6;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -248,17 +250,16 @@ __device__ void setup_block(float *D, int n, int R, float *tile, uint32_t &bad, 
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int row = R * 64 + wv + W * p;
-            x[p] = (row < n && col < n && col > row) ? D[(size_t)row * n + col] : 0.0f;
+            x[p] = (row < n && col < n && col > row) ? src[(size_t)row * n + col] : 0.0f;
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int rr = wv + W * p, row = R * 64 + rr;
             if (row < n && col < n && col > row) {
                 if (!(fabsf(x[p]) <= 0x1p100f)) bad = 1;
-                if (__float_as_uint(x[p]) == 0x80000000u) {
-                    x[p] = 0.0f;
-                    D[(size_t)row * n + col] = 0.0f;
-                }
+                const bool neg0 = __float_as_uint(x[p]) == 0x80000000u;
+                if (neg0) x[p] = 0.0f;
+                if (neg0 || src != D) D[(size_t)row * n + col] = x[p];
                 run[p] = umin64(run[p], ((uint64_t)ord32(x[p]) << 32) | ((uint64_t)col << 16));
             }
             tile[rr * (kTile + 1) + lane] = x[p];
@@ -901,7 +902,7 @@ __device__ void flush_stats(Control *ctl, Stats &st) {
 
 // Set-up for the single-instance path: workgroup b handles row blocks b and
 // T-1-b (equal numbers of tiles), writing each row's first minimum to rowkey.
-__global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I) {
+__global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I, const float *src) {
     __shared__ float tile[kTile * (kTile + 1)];
     const int n = I.n, T = (n + 63) >> 6;
     const int b = (int)blockIdx.x;
@@ -909,7 +910,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I) {
     for (int pass = 0; pass < 2; ++pass) {
         const int R = pass == 0 ? b : T - 1 - b;
         if (pass == 1 && R == b) break;
-        setup_block<kSetupBlock>(I.D, n, R, tile, bad, [&](int r, uint64_t v) {
+        setup_block<kSetupBlock>(src, I.D, n, R, tile, bad, [&](int r, uint64_t v) {
             const int row = R * 64 + r;
             if (row < n) I.rowkey[row] = v == kEmpty ? kEmptyRow : v;
         });
@@ -954,7 +955,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     uint32_t bad = 0;
     for (int lq = 0; lq < own_ch; ++lq) {
         const int R = chunk_of(lq, g, w);
-        setup_block<B>(I.D, n, R, L.tile, bad, [&](int r, uint64_t v) {
+        setup_block<B>(I.D, I.D, n, R, L.tile, bad, [&](int r, uint64_t v) {
             L.cache[lq * 64 + r] = v == kEmpty ? kEmptyRow : v;
         });
     }
@@ -1329,10 +1330,10 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_run(const Instance &inst, int g, int block, Control *ctl, uint64_t timeout_ticks,
-                      hipStream_t stream, hipEvent_t setup_done) {
+hipError_t launch_run(const Instance &inst, const float *src, int g, int block, Control *ctl,
+                      uint64_t timeout_ticks, hipStream_t stream, hipEvent_t setup_done) {
     const int T = (inst.n + 63) / 64;
-    hipLaunchKernelGGL(k_setup, dim3((T + 1) / 2), dim3(kSetupBlock), 0, stream, inst);
+    hipLaunchKernelGGL(k_setup, dim3((T + 1) / 2), dim3(kSetupBlock), 0, stream, inst, src);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (setup_done) {
