@@ -11,6 +11,7 @@ namespace hac {
 constexpr int kRunBlock = 1024;      // default threads per workgroup of the single-instance kernel (256, 512 or 1024)
 constexpr int kBatchBlock = 256;     // default threads per workgroup of the batch kernel (256 or 1024)
 constexpr int kSetupBlock = 256;     // threads per workgroup of the set-up kernel
+constexpr int kSetupStrip = 4;       // tiles per workgroup of the set-up kernel
 constexpr int kChunk = 64;           // rows owned in chunks of 64 (one wave's lanes)
 constexpr int kTile = 64;            // mirror tile edge
 constexpr int kSlotStride = 512;     // u64 words between exchange slots (4 KiB)

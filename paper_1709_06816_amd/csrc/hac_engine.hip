@@ -228,23 +228,24 @@ __device__ unsigned long long block_sum(unsigned long long v) {
     return r;
 }
 
-// Set-up of row block R (rows 64R .. 64R+63), playing the part of the
-// paper's initial distribution of the matrix: for every tile (R, C >= R)
-// read the strict-upper entries from src, validate and canonicalise them,
+// Set-up of row block R (rows 64R .. 64R+63) over tile columns
+// c_begin .. c_end-1 (c_begin >= R), playing the part of the paper's initial
+// distribution of the matrix: for every tile (R, C) read the strict-upper
+// entries from src, validate and canonicalise them,
 // store them in D (when D is not src, or to canonicalise -0), mirror them
 // into tile (C, R) of D, and keep each row's running minimum.  Hands the
-// minimum key (ord : 32 | column : 16) of row 64R + r to `sink(r, key)`
-// (lane 0 of the wave holding that row; kEmpty if the row has no entry to
-// its right).  The diagonal of D is never written (nor read later).
+// minimum key (ord : 32 | column : 16) of row 64R + r over those columns to
+// `sink(r, key)` (lane 0 of the wave holding that row; kEmpty if the row has
+// no entry there).  The diagonal of D is never written (nor read later).
 template <int B, class Sink>
-__device__ void setup_block(const float *src, float *D, int n, int R, float *tile, uint32_t &bad, Sink sink) {
+__device__ void setup_block(const float *src, float *D, int n, int R, int c_begin, int c_end, float *tile,
+                            uint32_t &bad, Sink sink) {
     constexpr int W = B / 64, P = 64 / W;  // rows of a tile per wave
-    const int T = (n + 63) >> 6;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint64_t run[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) run[p] = kEmpty;
-    for (int C = R; C < T; ++C) {
+    for (int C = c_begin; C < c_end; ++C) {
         float x[P];
         const int col = C * 64 + lane;
 #pragma unroll
@@ -900,21 +901,24 @@ __device__ void flush_stats(Control *ctl, Stats &st) {
     }
 }
 
-// Set-up for the single-instance path: workgroup b handles row blocks b and
-// T-1-b (equal numbers of tiles), writing each row's first minimum to rowkey.
+// Set-up for the single-instance path: workgroup (x, R) handles the strip of
+// up to kSetupStrip tiles (R, R + x*kSetupStrip ...) of row block R, so that
+// the pass over the upper triangle has many workgroups per CU; each row's
+// first minimum is the atomic minimum of its strips' minima in rowkey
+// (filled with kEmpty beforehand).
 __global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I, const float *src) {
     __shared__ float tile[kTile * (kTile + 1)];
     const int n = I.n, T = (n + 63) >> 6;
-    const int b = (int)blockIdx.x;
+    const int R = (int)blockIdx.y;
+    const int c0 = R + (int)blockIdx.x * kSetupStrip;
+    if (c0 >= T) return;
+    const int c1 = c0 + kSetupStrip < T ? c0 + kSetupStrip : T;
     uint32_t bad = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        const int R = pass == 0 ? b : T - 1 - b;
-        if (pass == 1 && R == b) break;
-        setup_block<kSetupBlock>(src, I.D, n, R, tile, bad, [&](int r, uint64_t v) {
-            const int row = R * 64 + r;
-            if (row < n) I.rowkey[row] = v == kEmpty ? kEmptyRow : v;
-        });
-    }
+    setup_block<kSetupBlock>(src, I.D, n, R, c0, c1, tile, bad, [&](int r, uint64_t v) {
+        const int row = R * 64 + r;
+        if (row < n && v != kEmpty)
+            atomicMin(reinterpret_cast<unsigned long long *>(I.rowkey + row), (unsigned long long)v);
+    });
     if (bad) atomicOr(I.status, kErrInput);
 }
 
@@ -933,7 +937,8 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
     const int own_ch = own_chunks(n, g, w);
     for (int li = threadIdx.x; li < own_cap; li += B) {
         const int k = row_of_local(li, g, w);
-        L.cache[li] = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmptyRow;
+        const uint64_t v = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmpty;
+        L.cache[li] = v == kEmpty ? kEmptyRow : v;
     }
     __syncthreads();
     merge_loop<B, kMode>(I, g, w, L, ctl, timeout, st, 0u, false);
@@ -955,7 +960,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     uint32_t bad = 0;
     for (int lq = 0; lq < own_ch; ++lq) {
         const int R = chunk_of(lq, g, w);
-        setup_block<B>(I.D, I.D, n, R, L.tile, bad, [&](int r, uint64_t v) {
+        setup_block<B>(I.D, I.D, n, R, R, (n + 63) >> 6, L.tile, bad, [&](int r, uint64_t v) {
             L.cache[lq * 64 + r] = v == kEmpty ? kEmptyRow : v;
         });
     }
@@ -1224,6 +1229,12 @@ __global__ void k_zero(uint32_t *p, size_t words) {
         p[q] = 0u;
 }
 
+__global__ void k_fill_ones(uint32_t *p, size_t words) {
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < words;
+         q += (size_t)gridDim.x * blockDim.x)
+        p[q] = 0xFFFFFFFFu;
+}
+
 }  // namespace
 
 int own_rows(int n, int g) { return ((((n + 63) >> 6) + g - 1) / g) * 64; }
@@ -1333,7 +1344,15 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream) {
 hipError_t launch_run(const Instance &inst, const float *src, int g, int block, Control *ctl,
                       uint64_t timeout_ticks, hipStream_t stream, hipEvent_t setup_done) {
     const int T = (inst.n + 63) / 64;
-    hipLaunchKernelGGL(k_setup, dim3((T + 1) / 2), dim3(kSetupBlock), 0, stream, inst, src);
+    {
+        const size_t words = (size_t)inst.n * 2;  // rowkey: n u64 set to kEmpty
+        int grid = (int)((words + 255) / 256);
+        if (grid > 1024) grid = 1024;
+        hipLaunchKernelGGL(k_fill_ones, dim3(grid), dim3(256), 0, stream, reinterpret_cast<uint32_t *>(inst.rowkey),
+                           words);
+    }
+    hipLaunchKernelGGL(k_setup, dim3((T + kSetupStrip - 1) / kSetupStrip, T), dim3(kSetupBlock), 0, stream, inst,
+                       src);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (setup_done) {
