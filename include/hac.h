@@ -158,16 +158,15 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        (instance count, plan, workspace) and relaunched with
  *                        the new descriptors (1 = on, the default; 0 = plain
  *                        stream launches).  Results are identical either way.
- *   HAC_OPT_DEFER        hac_run on more than one workgroup: a row whose cached
- *                        partner merged keeps its old minimum as a lower bound
- *                        and is rescanned while its workgroup waits for the
- *                        next argmin, instead of before the next update.
- *                        0 = never, 1 = with 8 or more workgroups (the
- *                        default; fewer gain nothing), 2 = with any number.  A
- *                        bound that wins an argmin forces the workgroups to
- *                        rescan their stale rows and repeat that argmin, so
- *                        the merge list is the same either way (Section 4
- *                        step 1).
+ *   HAC_OPT_DEFER        hac_run: a row whose cached partner merged keeps its
+ *                        old minimum as a lower bound instead of being
+ *                        rescanned at once; only when such a bound wins an
+ *                        argmin do the workgroups rescan all their stale rows
+ *                        and repeat that argmin, so the merge list is the same
+ *                        either way (Section 4 step 1).  0 = never, 1 = on
+ *                        groups of two or more workgroups (the default; a
+ *                        workgroup alone does better rescanning at once),
+ *                        2 = also on one workgroup.
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,

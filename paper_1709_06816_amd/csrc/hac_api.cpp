@@ -19,7 +19,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultSingleWgN = 1536;
-constexpr int kDeferMinGroup = 8;       // HAC_OPT_DEFER = 1: defer from this many workgroups on
+constexpr int kDeferMinGroup = 2;       // HAC_OPT_DEFER = 1: defer from this many workgroups on
 constexpr int64_t kDefaultTimeoutMs = 10000;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -565,6 +565,8 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
         if (hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max)
             return fail(c, HAC_EDEVICE, "n=%d needs more co-resident workgroups than the device holds", n);
         if (g > 1 && !c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
+    } else if (c->opt_defer == 2 && !(flags & HAC_MODE_SCAN)) {
+        run_flags |= hac::kFlagDefer;  // one workgroup, deferred rescans on request
     }
 
     // Workspace: control | status | first row minima | slots.
@@ -606,10 +608,9 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     inst.n = n;
     inst.link = linkage;
     inst.exchange = (int32_t)c->opt_exchange;
-    // Deferred rescans pay from about 8 workgroups on (measured at n = 2048 …
-    // 32768); on fewer, each workgroup's stale rows outrun one background
-    // rescan per merge and forced rounds pile up.
-    if (g == 1 || (c->opt_defer == 1 && g < kDeferMinGroup)) run_flags &= ~hac::kFlagDefer;
+    // Deferred rescans pay on every group of workgroups (measured at n = 2048
+    // … 65536); a workgroup alone does better rescanning at once.
+    if (c->opt_defer == 1 && g < kDeferMinGroup) run_flags &= ~hac::kFlagDefer;
     inst.flags = run_flags;
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 

@@ -185,11 +185,6 @@ __shared__ uint64_t s_red[2][kMaxWaves];
 __shared__ uint64_t s_acc[2][4];
 __shared__ uint32_t s_nresc;
 __shared__ uint32_t s_fail;
-// Deferred rescans: the smallest key (bound : 32 | row : 16 | 0) over this
-// workgroup's stale rows, reduced with the candidates, and the minimum the
-// rescan of that row during the next exchange accumulates.
-__shared__ uint64_t s_bgkey;
-__shared__ uint64_t s_bgacc[2];
 __shared__ int s_inst;
 
 // Minimum of (a, b) over the workgroup, returned to every thread.
@@ -335,15 +330,11 @@ __device__ bool get_slot(const uint64_t *s, uint64_t gen, uint64_t &p1, uint64_t
 // Publish this workgroup's candidates of epoch e (s_acc[e&1][0..1]), wait for
 // the rest of the group, and leave the group-wide minima in s_acc[e&1][2..3]
 // (Section 5.3 steps 2-4: every processor ends up with the same global
-// minimum).  Waves other than wave 0 run `bg()` meanwhile (whole waves; it
-// must not touch s_acc).  Ends with a barrier.  Returns false if the wait was
-// abandoned; the decision is the same for every thread.
-struct NoBg {
-    __device__ void operator()() const {}
-};
-template <int B, class Bg = NoBg>
+// minimum).  Ends with a barrier.  Returns false if the wait was abandoned;
+// the decision is the same for every thread.
+template <int B>
 __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Control *ctl,
-                               uint64_t timeout, Bg bg = Bg()) {
+                               uint64_t timeout) {
     const int b = e & 1;
     const uint64_t gen = e & 0xFFFFu;
     uint64_t *base = I.slots + (size_t)b * (g + 1) * kSlotStride;
@@ -370,8 +361,6 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             lds_min(&s_acc[b][2], m1);
             lds_min(&s_acc[b][3], m2);
-        } else {
-            bg();
         }
         __syncthreads();
         if (I.exchange == kExchReducer && threadIdx.x == 0 && !s_fail) {
@@ -385,8 +374,6 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_acc[b][2] = m1;
             s_acc[b][3] = m2;
-        } else if (threadIdx.x >= 64) {
-            bg();
         }
         __syncthreads();
     }
@@ -540,19 +527,15 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // order: any other column attaining the old minimum lies to the right of the
 // old partner.
 //
-// kLoopDefer (g > 1) takes those rescans off the merge's critical path: such a
-// row becomes stale, keeping its old minimum as a lower bound (lowered by
-// every new entry it receives, so it stays a bound whatever the linkage), and
+// kLoopDefer takes those rescans off the merge's critical path: such a row
+// becomes stale, keeping its old minimum as a lower bound (lowered by every
+// new entry it receives, so it stays a bound whatever the linkage), and
 // offers (bound, k, 0) to the argmin, a key below any the row can really
-// have.  After each update every workgroup rescans its stale row of smallest
-// key (chosen while classifying) over l != i, with waves 1.. while wave 0
-// folds the candidates, publishes them and waits in the exchange; the update
-// has already folded the row's new (v_k, i) into the same accumulator.
-// Nobody else writes that row meanwhile (it is neither the merged row nor
-// written by another workgroup outside merges of it), so the result is its
-// exact minimum after this merge, taken over when the next merge classifies.
-// When a stale key wins an argmin anyway, every workgroup rescans all its
-// stale rows and the argmin is repeated (an extra exchange).
+// have.  A stale row is rescanned only when a stale key wins an argmin: then
+// every workgroup rescans all its stale rows at once and the argmin is
+// repeated (an extra exchange, a "forced round").  Most bounds never win
+// before their row merges or falls behind, and the rescans that are needed
+// run batched, in parallel over the workgroups.
 //
 // kLoopScan drops the cache: before every argmin every workgroup rescans all
 // its live rows, as Section 5.3 step 1 scans the whole matrix.
@@ -574,8 +557,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         for (int b = 0; b < 2; ++b)
             for (int q = 0; q < 4; ++q) s_acc[b][q] = kEmpty;
         s_nresc = 0;
-        s_bgkey = kEmpty;
-        s_bgacc[0] = s_bgacc[1] = kEmptyRow;
     }
     __syncthreads();
     // Exchange epochs after epoch0 (used by the caller) are taken one by one:
@@ -584,33 +565,12 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     uint32_t e = epoch0;
     fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(e + 1) & 1][0]);
     __syncthreads();  // later candidates are folded inside the update loop
-    // Deferred mode: the stale row rescanned during the coming exchange
-    // (local index, row, column skipped) and its accumulator s_bgacc[s & 1].
-    int li_bg = -1, k_bg = 0, skip_bg = -1;
     int i_prev = -1;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
         ++e;
         int b = e & 1;
-        uint64_t *bgacc = &s_bgacc[(s + 1) & 1];  // the row chosen by the last merge
-        if (defer) {
-            // This workgroup's candidates (wave 0) and the last update are
-            // complete; s_acc[b ^ 1] is cleared below, after the exchange.
-            auto bg = [&]() {
-                if (li_bg < 0) return;
-                scan_row<B, 1>(D, n, k_bg, L.amask, skip_bg, 0, bgacc, st.rescan_elems, coh);
-            };
-            if (g > 1) {
-                if (!group_exchange<B>(I, g, w, e, ctl, timeout, bg)) return;
-            } else {
-                if (tid >= 64) bg();
-                __syncthreads();
-            }
-            if (tid == 0) {
-                st.rescans += li_bg >= 0;
-                for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;  // for epoch e+1
-            }
-        } else if (scan) {
+        if (scan) {
             // The other parity's accumulators were last read before the last
             // barrier of the previous merge; clear them for epoch e+1.
             if (tid == 0)
@@ -618,9 +578,9 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             __syncthreads();
             if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout)) return;
         } else {
-            // The candidates were folded during the last update.  Alone, a
-            // workgroup still needs a barrier here: thread 0's size update of
-            // the last merge is read below.
+            // The candidates were folded during the last update (and are
+            // published at once).  Alone, a workgroup still needs a barrier
+            // here: thread 0's size update of the last merge is read below.
             if (g > 1) {
                 if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
             } else {
@@ -645,10 +605,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             if (tid == 0 && i_prev >= 0 && owner_of_row(i_prev, g) == w) L.cache[local_of_row(i_prev, g)] = ip_entry;
             for (int li = tid; li < own_ch * 64; li += B) {
                 const int k = row_of_local(li, g, w);
-                if (li == li_bg) {
-                    L.cache[li] = *bgacc;  // already rescanned
-                    continue;
-                }
                 if (k < n && k != i_prev && (L.cache[li] & kStale)) {
                     L.cache[li] = kEmptyRow;
                     L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
@@ -715,7 +671,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             atomicAnd(&L.amask[j >> 5], ~(1u << (j & 31)));
             if (owner_of_row(j, g) == w) L.cache[local_of_row(j, g)] = kEmptyRow;
         }
-        uint64_t stale_min = kEmpty;  // deferred mode: smallest stale key
         for (int li = tid; li < (scan ? 0 : own_ch * 64); li += B) {
             const int k = row_of_local(li, g, w);
             if (k >= n || k == i || k == j) continue;
@@ -725,16 +680,9 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 L.cache[li] = c;
             }
             if (defer) {
-                if (li == li_bg) {
-                    c = *bgacc;  // the row's exact minimum after the last merge
-                    L.cache[li] = c;
-                }
                 const int nn = (int)((c >> 16) & 0xFFFFull);
-                if (!(c & kStale) && (uint32_t)(c >> 32) != kEmptyOrd && (nn == i || nn == j)) {
-                    c = (c & kHi32) | kStale;  // keeps its old minimum as a bound
-                    L.cache[li] = c;
-                }
-                if (c & kStale) stale_min = umin64(stale_min, (c & kHi32) | ((uint64_t)k << 16));
+                if (!(c & kStale) && (uint32_t)(c >> 32) != kEmptyOrd && (nn == i || nn == j))
+                    L.cache[li] = (c & kHi32) | kStale;  // keeps its old minimum as a bound
                 continue;
             }
             const int nn = (int)((c >> 16) & 0xFFFFull);
@@ -743,7 +691,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
             }
         }
-        if (defer) lds_min(&s_bgkey, stale_min);
         __syncthreads();
         if (prof) st.lap(kPhUpdate);
         const uint32_t nresc = defer ? 0u : s_nresc;
@@ -752,15 +699,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             if (!scan) __syncthreads();  // rescanned entries are final before the update folds them
         }
         if (prof) st.lap(kPhRescan);
-        // The stale row rescanned during the next exchange.
-        int li_nx = -1, k_nx = -1;
-        if (defer) {
-            const uint64_t bk = s_bgkey;
-            if (bk != kEmpty) {
-                k_nx = (int)((bk >> 16) & 0xFFFFull);
-                li_nx = local_of_row(k_nx, g);
-            }
-        }
 
         // ---- Lance-Williams update of row/column i (Section 4 step 3) -----
         float ai = 0.0f, aj = 0.0f;
@@ -814,9 +752,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                     if (k < i) {  // the row's new entry at column i (see above)
                         c = umin64(c, (c & kStale) ? (((uint64_t)ord32(v) << 32) | kStale) : key);
                         *ce = c;
-                        // The rescan of the chosen row skips column i: its
-                        // new entry goes into the accumulator here.
-                        if (k == k_nx) s_bgacc[s & 1] = umin64(s_bgacc[s & 1], key);
                     }
                     if ((uint32_t)(c >> 32) != kEmptyOrd)
                         pc = umin64(pc, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
@@ -842,10 +777,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             L.size1[i] = (uint16_t)(ni + nj - 1);
             st.rescans += nresc;
             s_nresc = 0;
-            if (defer) {
-                *bgacc = kEmptyRow;  // taken over by the classification above
-                s_bgkey = kEmpty;    // read by every thread before the update
-            }
         }
         if (prof) st.lap(kPhCand);
 
@@ -873,12 +804,6 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 s_nresc = 0;
             }
             fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b ^ 1][0]);
-        } else if (defer) {
-            // The local candidates for the next argmin were folded during the
-            // update; the next exchange publishes them at once.
-            li_bg = li_nx;
-            k_bg = k_nx;
-            skip_bg = i;
         }
         i_prev = i;
     }

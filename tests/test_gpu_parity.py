@@ -78,22 +78,25 @@ def _diff(a, b):
 EDGE_NS = [2, 3, 5, 63, 64, 65, 127, 129, 300, 1000]
 
 
+@pytest.mark.parametrize("defer", [1, 2])
 @pytest.mark.parametrize("link", LINKS)
 @pytest.mark.parametrize("n", EDGE_NS)
-def test_edge_sizes_single_wg(ctx, torch, n, link):
+def test_edge_sizes_single_wg(ctx, torch, n, link, defer):
+    """One workgroup: immediate rescans (defer = 1, the default there) and
+    deferred rescans on request (defer = 2)."""
     d = synth.mixture_8192(seed=1000 + n, n=n)
-    _say("edge single-wg n=%d %s" % (n, link))
-    got = _gpu_run(ctx, torch, d, link)
+    _say("edge single-wg n=%d %s defer=%d" % (n, link, defer))
+    got = _gpu_run(ctx, torch, d, link, defer=defer)
     exp = oracle.run_f32(d, link)
     assert _same(got, exp), _diff(got, exp)
 
 
-@pytest.mark.parametrize("defer", [1, 2])
+@pytest.mark.parametrize("defer", [1, 0])
 @pytest.mark.parametrize("link", LINKS)
 @pytest.mark.parametrize("n,wgs", [(65, 2), (129, 3), (300, 5), (1000, 7), (1000, 16), (2500, 40)])
 def test_edge_sizes_multi_wg(ctx, torch, n, wgs, link, defer):
-    """Groups of workgroups; defer = 1 (automatic: deferred rescans from 8
-    workgroups on) and 2 (deferred on any group)."""
+    """Groups of workgroups with deferred rescans (defer = 1, the default)
+    and on one workgroup and groups with immediate rescans (defer = 0)."""
     d = synth.mixture_8192(seed=2000 + n, n=n)
     _say("edge multi-wg n=%d wgs=%d %s defer=%d" % (n, wgs, link, defer))
     got = _gpu_run(ctx, torch, d, link, single_wg_n=1, workgroups=wgs, defer=defer)
@@ -222,11 +225,11 @@ def test_scan_mode_matches_oracle(ctx, torch, link):
 
 @pytest.mark.parametrize("link", LINKS)
 def test_deferred_rescans_match_oracle(ctx, torch, link):
-    """Multi-workgroup hac_run with rescans deferred into the exchange wait
-    (forced on with HAC_OPT_DEFER = 2, also below 8 workgroups), automatic
-    (the default) and immediate (HAC_OPT_DEFER = 0) give the oracle's bytes.
-    The tie-heavy quantised matrix makes stale lower bounds win argmins, so
-    the forced extra rounds run too."""
+    """Multi-workgroup hac_run with deferred rescans (stale rows keep lower
+    bounds and are rescanned only when a bound wins an argmin) in automatic
+    (the default: any group) and forced (HAC_OPT_DEFER = 2) mode, and with
+    immediate rescans (HAC_OPT_DEFER = 0), gives the oracle's bytes.  Stale
+    bounds win argmins on every input here, so the forced rounds run too."""
     import paper_1709_06816_amd as hac
     cases = [(synth.batch_instance(1000, 1001), 7), (synth.quantized_matrix(700, 703), 8),
              (synth.rmsd_like(seed=77, n=700), 9), (synth.quantized_matrix(1500, 1507, levels=4), 24),
@@ -245,7 +248,7 @@ def test_deferred_rescans_match_oracle(ctx, torch, link):
                 got = ctx.run(t, link, preserve=True)
                 st = ctx.stats()
                 assert st["workgroups"] == wgs
-                assert st["deferred"] == (defer == 2 or (defer == 1 and wgs >= 8))
+                assert st["deferred"] == (defer == 2 or (defer == 1 and wgs >= 2))
                 assert _same(got, exp), (n, wgs, defer, _diff(got, exp))
                 if defer == 2:
                     forced[n] = st["forced_rounds"]
