@@ -1,17 +1,22 @@
 // Device engine: Lance-Williams agglomerative clustering on gfx950.
 //
-// Three kernels:
+// Kernels:
 //   k_setup   (single-instance path) validates and canonicalises the strict
-//             upper triangle, mirrors it into the lower triangle and writes
-//             each row's first cached minimum; it spreads the O(n^2) pass over
-//             the whole device.
+//             upper triangle, mirrors it into the lower triangle (or writes
+//             both triangles of a working copy) and computes each row's first
+//             cached minimum; it spreads the O(n^2) pass over the whole device.
 //   k_run     runs all n-1 merges of one instance on a group of g co-resident
-//             workgroups of 1024 threads (g = 1 for small n).
+//             workgroups of 1024 threads (g = 1 for small n); template
+//             variants rescan rows at once, defer rescans behind lower bounds,
+//             or rescan everything every merge (Section 5.3 step 1).
 //   k_batch   runs many independent instances in one launch: the largest
 //             may each get a fixed group of workgroups (exchanging through
 //             their own slots), the rest take one workgroup each, largest
 //             first, from a queue; each workgroup does its instance's set-up
 //             itself.
+//   k_serve   a persistent server: workgroups take jobs that the host
+//             publishes in a ring in host memory, one workgroup or a group per
+//             job, until the host stops it.
 //
 // Data layout (one GPU, the whole matrix in HBM):
 //   * The n x n fp32 matrix is kept fully symmetric, row-major, so that both
@@ -32,15 +37,17 @@
 //            (steps 2-5 of Section 5.3).
 //   update   the owner of column k reads D[i][k], D[j][k] (row reads),
 //            applies the Table 1 update, writes D[i][k] (row) and D[k][i]
-//            (column, through symmetric storage), refreshes its cache entry
-//            for row k, and queues a rescan of row k when the cached partner
-//            was i or j and the new value cannot replace it (step 6).
+//            (column, through symmetric storage) and refreshes its cache
+//            entry for row k; a row whose cached partner was i or j is
+//            rescanned at once or, deferred, keeps a lower bound (step 6;
+//            see merge_loop).
 //   row i    its new minimum over l > i is reduced from the new values
 //            themselves and carried in the next exchange.
 // Exchange between workgroups: each workgroup writes three 64-bit words
 // tagged with a 16-bit generation into its own slot (double-buffered by
 // parity) after an agent-scope release fence; readers poll the slots and take
-// an agent-scope acquire fence.  One exchange per merge.
+// an agent-scope acquire fence.  One exchange per merge (plus one per forced
+// round of the deferred mode).
 #include <hip/hip_runtime.h>
 
 #include "hac_engine.h"
