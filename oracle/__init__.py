@@ -31,7 +31,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lw_oracle.c")
 LIB = os.path.join(HERE, "_lw_oracle.so")
 
-LINKAGES = {"single": 0, "complete": 1, "average": 2, "ward": 3}
+# Table 1 rows; "weighted" is the Weighted Average row (WPGMA).
+LINKAGES = {"single": 0, "complete": 1, "average": 2, "ward": 3, "weighted": 4, "centroid": 5}
 MERGE_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("h", "<f4"), ("size", "<i4")])
 MERGE64_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("h", "<f8"), ("size", "<i4")])
 
@@ -182,6 +183,13 @@ def linkage_from_members(d: np.ndarray, a, b, linkage) -> float:
                - mean_{BxB} D / 2), means over ordered pairs including the
                zero diagonal.  For squared Euclidean D this is the Ward
                merge cost 2|A||B|/(|A|+|B|) |c_A - c_B|^2.
+    centroid : mean_{AxB} D - mean_{AxA} D / 2 - mean_{BxB} D / 2 (same
+               means).  For squared Euclidean D this is |c_A - c_B|^2, the
+               squared distance between the centroids (the centroid method
+               named in Section 2.1); the Table 1 centroid row reproduces it
+               for any symmetric D with zero diagonal.
+    weighted : has no member-set form (it depends on the merge order) and is
+               rejected here.
     """
     link = _link(linkage)
     ab = d[np.ix_(a, b)]
@@ -191,10 +199,15 @@ def linkage_from_members(d: np.ndarray, a, b, linkage) -> float:
         return float(ab.max())
     if link == 2:
         return float(ab.mean())
+    if link == 4:
+        raise ValueError("weighted average has no member-set form")
     aa = d[np.ix_(a, a)]
     bb = d[np.ix_(b, b)]
     na, nb = len(a), len(b)
-    return 2.0 * na * nb / (na + nb) * (ab.mean() - 0.5 * aa.mean() - 0.5 * bb.mean())
+    f = ab.mean() - 0.5 * aa.mean() - 0.5 * bb.mean()
+    if link == 5:
+        return float(f)
+    return 2.0 * na * nb / (na + nb) * f
 
 
 def symmetric_from_upper(dist: np.ndarray) -> np.ndarray:

@@ -37,6 +37,17 @@
  *              beta = -n_k/T, gamma = 0.  fp32: coefficients are fp64
  *              quotients rounded once to fp32;
  *              v = ((a_i*D_ki) + (a_j*D_kj)) + (b*D_ij).
+ *   weighted : (Table 1 row "Weighted Average") alpha_i = alpha_j = 1/2,
+ *              beta = gamma = 0.  fp32: v = (0.5*D_ki) + (0.5*D_kj).
+ *   centroid : (Table 1 row "Centroid") alpha_i = n_i/(n_i+n_j),
+ *              alpha_j = n_j/(n_i+n_j), beta = -n_i*n_j/(n_i+n_j)^2, gamma = 0.
+ *              fp32: coefficients are fp64 quotients rounded once to fp32;
+ *              v = ((a_i*D_ki) + (a_j*D_kj)) + (b*D_ij).  Heights need not
+ *              increase and can be negative when the input is not a matrix
+ *              of squared Euclidean distances.  Values stay finite: D_ij is
+ *              the minimum over live pairs, so a negative minimum never
+ *              grows in magnitude and one merge adds at most |D_ij|/4 to any
+ *              entry; |D| stays below 2^100 * (1 + (n-1)/4).
  * A result equal to zero is stored as +0.
  *
  * Input: the strict upper triangle of the row-major n x n matrix is
@@ -53,8 +64,9 @@
 #include <omp.h>
 #endif
 
-enum { OR_SINGLE = 0, OR_COMPLETE = 1, OR_AVERAGE = 2, OR_WARD = 3 };
+enum { OR_SINGLE = 0, OR_COMPLETE = 1, OR_AVERAGE = 2, OR_WARD = 3, OR_WEIGHTED = 4, OR_CENTROID = 5 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EINPUT = -2, OR_ENOMEM = -3, OR_EINTERNAL = -4 };
+#define OR_MAX_LINK 5
 
 #define OR_MAX_ABS 1.2676506002282294e30 /* 2^100 */
 
@@ -77,6 +89,20 @@ static float lw_f32(int link, float dki, float dkj, float dij,
         float t1 = ai * dki;
         float t2 = aj * dkj;
         v = t1 + t2;
+    } else if (link == OR_WEIGHTED) {
+        float t1 = 0.5f * dki;
+        float t2 = 0.5f * dkj;
+        v = t1 + t2;
+    } else if (link == OR_CENTROID) {
+        double s = (double)(ni + nj);
+        float ai = (float)((double)ni / s);
+        float aj = (float)((double)nj / s);
+        float b = (float)(-((double)ni * (double)nj) / (s * s));
+        float t1 = ai * dki;
+        float t2 = aj * dkj;
+        float t3 = b * dij;
+        float u = t1 + t2;
+        v = u + t3;
     } else { /* OR_WARD */
         double t = (double)(ni + nj + nk);
         float ai = (float)((double)(ni + nk) / t);
@@ -104,6 +130,11 @@ static double lw_f64(int link, double dki, double dkj, double dij,
     } else if (link == OR_AVERAGE) {
         double s = (double)(ni + nj);
         v = ((double)ni / s) * dki + ((double)nj / s) * dkj;
+    } else if (link == OR_WEIGHTED) {
+        v = 0.5 * dki + 0.5 * dkj;
+    } else if (link == OR_CENTROID) {
+        double s = (double)(ni + nj);
+        v = (((double)ni / s) * dki + ((double)nj / s) * dkj) + (-((double)ni * (double)nj) / (s * s)) * dij;
     } else {
         double t = (double)(ni + nj + nk);
         v = (((double)(ni + nk) / t) * dki + ((double)(nj + nk) / t) * dkj)
@@ -135,7 +166,7 @@ int lw_oracle_f32(const float *dist, int64_t n, int link, int64_t max_merges,
                   int nthreads, int64_t *merges_done)
 {
     if (merges_done) *merges_done = 0;
-    if (n < 1 || !dist || link < 0 || link > 3) return OR_EINVAL;
+    if (n < 1 || !dist || link < 0 || link > OR_MAX_LINK) return OR_EINVAL;
     int64_t want = n - 1;
     if (max_merges >= 0 && max_merges < want) want = max_merges;
     if (want > 0 && (!out_i || !out_j || !out_h || !out_size)) return OR_EINVAL;
@@ -206,7 +237,7 @@ int lw_oracle_f64(const double *dist, int64_t n, int link, int64_t max_merges,
                   int nthreads, int64_t *merges_done)
 {
     if (merges_done) *merges_done = 0;
-    if (n < 1 || !dist || link < 0 || link > 3) return OR_EINVAL;
+    if (n < 1 || !dist || link < 0 || link > OR_MAX_LINK) return OR_EINVAL;
     int64_t want = n - 1;
     if (max_merges >= 0 && max_merges < want) want = max_merges;
     if (want > 0 && (!out_i || !out_j || !out_h || !out_size)) return OR_EINVAL;
@@ -279,7 +310,7 @@ int lw_replay_f64(const float *dist, int64_t n, int link, int64_t count,
                   const int32_t *mi, const int32_t *mj, double *h64,
                   double *min64, int64_t opt_stride, int nthreads)
 {
-    if (n < 1 || !dist || link < 0 || link > 3 || count < 0 || count > n - 1)
+    if (n < 1 || !dist || link < 0 || link > OR_MAX_LINK || count < 0 || count > n - 1)
         return OR_EINVAL;
     double *w = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
     int64_t *sz = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);

@@ -13,6 +13,9 @@ mathematics fix rather than against the oracle itself.
   fp64 replay error bound and optimality                    test_fp64_replay_bounds
   library hierarchical clustering cross-check               test_scipy_cross_check
   input conventions (upper triangle, -0, non-finite)        test_input_*
+  centroid: member formula vs |c_A - c_B|^2, brute force    test_centroid_*
+  weighted average: exact fp32 special cases, library       test_weighted_*, test_scipy_cross_check
+  centroid bound on extreme inputs                          test_centroid_extreme_inputs_finite
 """
 import json
 import os
@@ -26,6 +29,9 @@ from conftest import matrix_from_upper
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LINKS = ["single", "complete", "average", "ward"]
+# Table 1 rows Weighted Average and Centroid.
+EXTRA = ["weighted", "centroid"]
+ALL = LINKS + EXTRA
 
 
 def _golden():
@@ -34,7 +40,7 @@ def _golden():
 
 
 @pytest.mark.parametrize("case", _golden(), ids=lambda c: c["name"])
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", ALL)
 def test_hand_worked(case, link):
     d = matrix_from_upper(case["n"], case["upper"])
     got = oracle.run_f32(d, link)
@@ -66,19 +72,22 @@ def _small_inputs():
     return out
 
 
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", LINKS + ["centroid"])
 def test_brute_force_f32(link):
     """Every fp32 merge height equals the linkage recomputed from raw member
     sets; every chosen pair is minimal; single/complete ties resolve to the
     smallest (i, j)."""
     for kind, seed, d in _small_inputs():
         m = oracle.run_f32(d, link)
-        errs = oracle.brute_force_check(d, m, link, rtol=2e-6, atol=1e-6,
+        # centroid values can cancel towards zero on non-Euclidean input:
+        # the absolute slack scales with the input's magnitude
+        atol = 1e-6 if link != "centroid" else 2e-6 * float(np.abs(d).max())
+        errs = oracle.brute_force_check(d, m, link, rtol=2e-6, atol=atol,
                                         exact_ties=link in ("single", "complete"))
         assert not errs, (kind, seed, errs[:3])
 
 
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", LINKS + ["centroid"])
 def test_brute_force_f64(link):
     for kind, seed, d in _small_inputs():
         m = oracle.run_f64(d, link)
@@ -99,6 +108,50 @@ def test_ward_member_formula():
         want = 2.0 * len(a) * len(b) / (len(a) + len(b)) * ((ca - cb) ** 2).sum()
         got = oracle.linkage_from_members(d2, a, b, "ward")
         assert abs(got - want) <= 1e-12 * want
+
+
+def test_centroid_member_formula():
+    """The member-set centroid formula used by the brute-force checker equals
+    the squared distance between the two clusters' centroids on squared
+    Euclidean distances (closed form from the points)."""
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((9, 4))
+    d2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    for a, b in ([[0, 1, 2], [3, 4]], [[5], [6, 7, 8]], [[1], [2]]):
+        want = ((x[a].mean(0) - x[b].mean(0)) ** 2).sum()
+        got = oracle.linkage_from_members(d2, a, b, "centroid")
+        assert abs(got - want) <= 1e-12 * want
+    with pytest.raises(ValueError):
+        oracle.linkage_from_members(d2, [0], [1], "weighted")
+
+
+def test_centroid_heights_are_centroid_distances():
+    """On squared Euclidean input every fp64 centroid height is the squared
+    distance between the centroids of the two member sets, recomputed from
+    the points (not from the matrix)."""
+    rng = np.random.default_rng(31)
+    x = synth.gaussian_mixture(rng, 120, 4, 5).astype(np.float64)
+    d2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    m = oracle.run_f64(d2, "centroid")
+    members = {k: [k] for k in range(len(x))}
+    for r in m:
+        a, b = members[int(r["i"])], members[int(r["j"])]
+        want = ((x[a].mean(0) - x[b].mean(0)) ** 2).sum()
+        assert abs(r["h"] - want) <= 1e-10 * want + 1e-12
+        members[int(r["i"])] = a + b
+        del members[int(r["j"])]
+
+
+def test_centroid_extreme_inputs_finite():
+    """The merged pair holds the minimum, so a negative minimum never grows in
+    magnitude and one merge adds at most a quarter of it to any entry: inputs
+    at the accepted limit 2^100 of either sign stay finite in fp32."""
+    rng = np.random.default_rng(5)
+    n = 300
+    d = (rng.choice([-1.0, 1.0], size=(n, n)) * 2.0 ** 100).astype(np.float32)
+    m = oracle.run_f32(d, "centroid")
+    assert len(m) == n - 1 and np.all(np.isfinite(m["h"]))
+    assert np.all(np.abs(m["h"].astype(np.float64)) <= 2.0 ** 100 * (1 + (n - 1) / 4))
 
 
 def test_single_is_prim_mst():
@@ -128,24 +181,26 @@ def test_prim_matches_scipy():
     assert np.allclose(np.sort(ref[ref > 0]), np.sort(oracle.prim_mst_weights(d)))
 
 
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", LINKS + ["weighted"])
 def test_monotone_heights(link):
-    """For the four reducible linkages heights never decrease: exactly for
-    single/complete, up to 1e-6 relative for fp32 average/Ward (fp32
-    coefficients need not sum to one)."""
+    """For the five reducible linkages heights never decrease: exactly for
+    single/complete and for weighted average (halving is exact and a rounded
+    sum of two halves lies between them), up to 1e-6 relative for fp32
+    average/Ward (fp32 coefficients need not sum to one)."""
     for seed in range(3):
         d = synth.mixture_8192(seed=seed, n=400)
         m = oracle.run_f32(d, link)
-        rel = 0.0 if link in ("single", "complete") else 1e-6
+        rel = 0.0 if link in ("single", "complete", "weighted") else 1e-6
         assert oracle.monotone_violations(m, rel) == 0
         m64 = oracle.run_f64(d, link)
         assert oracle.monotone_violations(m64, 0.0 if link != "ward" else 1e-12) == 0
 
 
-@pytest.mark.parametrize("link", ["single", "complete"])
+@pytest.mark.parametrize("link", ["single", "complete", "weighted"])
 def test_constant_matrix(link):
     """All distances equal c: every step is a tie, the smallest (i, j) wins,
-    so the list is (0, k, c, k+1)."""
+    so the list is (0, k, c, k+1) (weighted average: 0.5c + 0.5c is exactly c
+    in fp32)."""
     n, c = 37, np.float32(2.5)
     d = np.full((n, n), c, np.float32)
     m = oracle.run_f32(d, link)
@@ -166,11 +221,12 @@ def test_constant_matrix_f64(link):
     assert np.array_equal(m["size"][-1:], [n])
 
 
-@pytest.mark.parametrize("link", ["single", "complete", "average"])
+@pytest.mark.parametrize("link", ["single", "complete", "average", "weighted"])
 def test_ultrametric(link):
     """On an ultrametric, all cross distances between two clusters that are
-    merged are equal, so single, complete and average reproduce its levels:
-    the sorted heights are the sorted distinct levels."""
+    merged are equal, so single, complete, average and weighted average
+    reproduce its levels: the sorted heights are the sorted distinct levels
+    (weighted average exactly in fp32: the mean of two equal values)."""
     for seed in range(3):
         d = synth.ultrametric_matrix(40, seed)
         levels = np.unique(d[np.triu_indices(40, 1)])
@@ -180,7 +236,7 @@ def test_ultrametric(link):
         assert np.allclose(np.sort(m["h"]), levels, rtol=tol, atol=0)
 
 
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", ALL)
 def test_relabel_invariance(link):
     """Permuting the items leaves the set of (member set, height) merges
     unchanged on tie-free input: every recipe is symmetric in i <-> j and uses
@@ -195,7 +251,7 @@ def test_relabel_invariance(link):
     assert sorted(a) == sorted(b)
 
 
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", ALL)
 def test_fp64_replay_bounds(link):
     """Replaying the fp32 list in fp64: heights within 1e-5 relative, and each
     chosen pair within 1e-5 relative of the fp64 minimum over live pairs."""
@@ -207,11 +263,13 @@ def test_fp64_replay_bounds(link):
         assert np.all(h64 <= min64 + 1e-5 * np.abs(min64))
 
 
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", ALL)
 def test_scipy_cross_check(link):
     """Library hierarchical clustering on tie-free input: same heights.  For
-    Ward, Table 1 applied to D o D gives the squared minimum-variance costs,
-    so sqrt of our heights on D o D equals the library's ward heights."""
+    Ward and centroid, Table 1 applied to D o D gives the squared
+    minimum-variance costs and squared centroid distances, so sqrt of our
+    heights on D o D equals the library's heights (which it computes from
+    Euclidean distances)."""
     from scipy.cluster.hierarchy import linkage as sp_linkage
     from scipy.spatial.distance import squareform
     n = 200
@@ -219,15 +277,16 @@ def test_scipy_cross_check(link):
     x = rng.standard_normal((n, 6))
     d64 = np.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1))
     np.fill_diagonal(d64, 0)
-    if link == "ward":
+    sq = link in ("ward", "centroid")
+    if sq:
         ours = np.sqrt(oracle.run_f64(d64 * d64, link)["h"])
     else:
         ours = oracle.run_f64(d64, link)["h"]
     ref = sp_linkage(squareform(d64, checks=False), method=link)[:, 2]
     assert np.allclose(np.sort(ours), np.sort(ref), rtol=1e-10, atol=0)
-    ours32 = oracle.run_f32(d64.astype(np.float32) if link != "ward"
+    ours32 = oracle.run_f32(d64.astype(np.float32) if not sq
                             else (d64 * d64).astype(np.float32), link)["h"].astype(np.float64)
-    if link == "ward":
+    if sq:
         ours32 = np.sqrt(ours32)
     assert np.allclose(np.sort(ours32), np.sort(ref), rtol=2e-5, atol=0)
 
@@ -298,7 +357,7 @@ def test_thread_count_invariance():
     assert a.tobytes() == b.tobytes()
 
 
-@pytest.mark.parametrize("link", LINKS)
+@pytest.mark.parametrize("link", ALL)
 def test_replay_reproduces_fp64_oracle(link):
     """The fp64 replay checker, fed the fp64 oracle's own merge list, must
     return exactly the oracle's heights, and every listed pair must be the
