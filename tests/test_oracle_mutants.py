@@ -2,7 +2,8 @@
 
 Each case copies oracle/lw_oracle.c, plants one mistake by a textual edit,
 builds it into a temporary library and runs the fp32 pins (hand-worked cases,
-brute force over member sets, tie-break on constant matrices, Prim MST)
+brute force over member sets, tie-break on constant matrices, Prim MST,
+library weighted-average clustering)
 against it.  At least one pin must fail for every planted mistake, and the
 unmodified source must pass all of them.
 """
@@ -18,7 +19,8 @@ import synth
 from conftest import matrix_from_upper
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LINKS = ["single", "complete", "average", "ward"]
+LINKS = ["single", "complete", "average", "ward", "weighted", "centroid"]
+BRUTE = ["single", "complete", "average", "ward", "centroid"]
 
 MUTANTS = {
     "ward_beta_sign": ("float b = (float)(-(double)nk / t);", "float b = (float)((double)nk / t);"),
@@ -34,6 +36,15 @@ MUTANTS = {
     "scan_skips_neighbour": ("for (int64_t b = a + 1; b < n; b++)\n                    if (alive[b]",
                              "for (int64_t b = a + 2; b < n; b++)\n                    if (alive[b]"),
     "survivor_keeps_j_alive": ("alive[j] = 0;", "alive[i] = 0;"),
+    "centroid_beta_sign": ("float b = (float)(-((double)ni * (double)nj) / (s * s));",
+                           "float b = (float)(((double)ni * (double)nj) / (s * s));"),
+    "centroid_beta_not_squared": ("float b = (float)(-((double)ni * (double)nj) / (s * s));",
+                                  "float b = (float)(-((double)ni * (double)nj) / s);"),
+    "centroid_drops_beta": ("v = u + t3;", "v = u;"),
+    "weighted_reads_i_twice": ("float t2 = 0.5f * dkj;", "float t2 = 0.5f * dki;"),
+    "weighted_uses_sizes": ("float t1 = 0.5f * dki;\n        float t2 = 0.5f * dkj;",
+                            "float t1 = (float)((double)ni / (double)(ni + nj)) * dki;\n"
+                            "        float t2 = (float)((double)nj / (double)(ni + nj)) * dkj;"),
 }
 
 
@@ -54,7 +65,7 @@ def _pins_fail(lib) -> list:
                     break
         for seed in range(3):
             for d in (synth.uniform_matrix(10, seed), synth.quantized_matrix(10, seed, 4)):
-                for link in LINKS:
+                for link in BRUTE:
                     m = oracle.run_f32(d, link, lib=lib)
                     if oracle.brute_force_check(d, m, link, rtol=2e-6, atol=1e-6,
                                                 exact_ties=link in ("single", "complete")):
@@ -68,6 +79,14 @@ def _pins_fail(lib) -> list:
         m = oracle.run_f32(d, "single", lib=lib)
         if not np.array_equal(np.sort(m["h"]), np.sort(oracle.prim_mst_weights(d))):
             failed.append("mst")
+        from scipy.cluster.hierarchy import linkage as sp_linkage
+        from scipy.spatial.distance import squareform
+        d = synth.uniform_matrix(40, 6)
+        d64 = np.triu(d, 1).astype(np.float64)
+        ref = sp_linkage(squareform(d64 + d64.T, checks=False), method="weighted")[:, 2]
+        got = oracle.run_f32(d, "weighted", lib=lib)["h"].astype(np.float64)
+        if not np.allclose(np.sort(got), np.sort(ref), rtol=1e-5, atol=0):
+            failed.append("library_weighted")
     except Exception as e:  # a crash or an error code also counts as caught
         failed.append("error:%s" % type(e).__name__)
     return failed
