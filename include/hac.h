@@ -23,10 +23,16 @@
  *     of the merged cluster.  Ties between equal distances go to the
  *     lexicographically smallest (i, j).
  *   - Arithmetic: fp32 storage; single/complete are min/max (exact);
- *     average and Ward evaluate the Table 1 formula in fp32 with
- *     coefficients computed as fp64 quotients rounded once to fp32 and the
- *     fixed order ((a_i*D_ki) + (a_j*D_kj)) [+ (beta*D_ij)], no fused
- *     multiply-add; a zero result is stored as +0.
+ *     average, weighted average, centroid and Ward evaluate the Table 1
+ *     formula in fp32 with coefficients computed as fp64 quotients rounded
+ *     once to fp32 (1/2 for weighted average) and the fixed order
+ *     ((a_i*D_ki) + (a_j*D_kj)) [+ (beta*D_ij)], no fused multiply-add; a
+ *     zero result is stored as +0.
+ *   - Centroid heights need not increase with the merge index, and are
+ *     negative where the input is not a matrix of squared Euclidean
+ *     distances.  They stay finite: the merged pair holds the minimum, so a
+ *     negative minimum never grows in magnitude and one merge adds at most
+ *     |D_ij|/4 to an entry, which bounds |D| by 2^100 * (1 + (n-1)/4).
  *   - n is limited to 1 <= n <= HAC_MAX_N.
  *   - Thread safety: one context per host thread.  Calls on one context are
  *     serialised by the caller.
@@ -49,7 +55,9 @@ typedef enum {
     HAC_SINGLE = 0,   /* Table 1 row "Single Linkage":   min(D_ki, D_kj) */
     HAC_COMPLETE = 1, /* Table 1 row "Complete Linkage": max(D_ki, D_kj) */
     HAC_AVERAGE = 2,  /* Table 1 row "Group Average" */
-    HAC_WARD = 3      /* Table 1 row "Ward" */
+    HAC_WARD = 3,     /* Table 1 row "Ward" */
+    HAC_WEIGHTED = 4, /* Table 1 row "Weighted Average": (D_ki + D_kj) / 2 */
+    HAC_CENTROID = 5  /* Table 1 row "Centroid" */
 } hac_linkage;
 
 typedef struct {

@@ -26,7 +26,8 @@ __all__ = ["HacError", "Context", "Server", "run", "batch", "to_linkage_matrix",
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libhac.so")
 
-LINKAGES = {"single": 0, "complete": 1, "average": 2, "ward": 3}
+# hac_linkage values; "weighted" is Table 1's Weighted Average row.
+LINKAGES = {"single": 0, "complete": 1, "average": 2, "ward": 3, "weighted": 4, "centroid": 5}
 MERGE_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("h", "<f4"), ("size", "<i4")])
 
 HAC_OK, HAC_EINVAL, HAC_EINPUT, HAC_ENOMEM, HAC_EDEVICE, HAC_ENODEV, HAC_EBUSY, \

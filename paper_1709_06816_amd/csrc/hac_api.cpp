@@ -225,18 +225,19 @@ namespace {
 constexpr int kGroupMinN = 2048;
 
 // Signature of a batch for the plan cache: size histogram (powers of two) and
-// linkage mix.
+// linkage mix (linkages already checked to be 0..HAC_CENTROID).
 std::string batch_signature(const int32_t *ns, const int32_t *links, int count) {
-    int hist[18] = {0}, lk[4] = {0};
+    constexpr int kLinks = HAC_CENTROID + 1;
+    int hist[18] = {0}, lk[kLinks] = {0};
     for (int k = 0; k < count; ++k) {
         int b = 0;
         while ((1 << (b + 1)) <= ns[k] && b < 17) ++b;
         hist[b]++;
-        lk[links[k] & 3]++;
+        lk[links[k]]++;
     }
     std::string s = std::to_string(count);
     for (int b = 0; b < 18; ++b) s += "," + std::to_string(hist[b]);
-    for (int q = 0; q < 4; ++q) s += ";" + std::to_string(lk[q]);
+    for (int q = 0; q < kLinks; ++q) s += ";" + std::to_string(lk[q]);
     return s;
 }
 
@@ -526,7 +527,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     c->err.clear();
     if (!dist) return fail(c, HAC_EINVAL, "dist is NULL");
     if (n < 1 || n > HAC_MAX_N) return fail(c, HAC_EINVAL, "n=%d outside 1..%d", n, HAC_MAX_N);
-    if (linkage < 0 || linkage > 3) return fail(c, HAC_EINVAL, "linkage %d is not 0..3", linkage);
+    if (linkage < 0 || linkage > HAC_CENTROID) return fail(c, HAC_EINVAL, "linkage %d is not 0..5", linkage);
     if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE | HAC_MODE_SCAN)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
     if (n > 1 && !out) return fail(c, HAC_EINVAL, "out is NULL");
     int rc = set_device(c);
@@ -642,7 +643,8 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     for (int k = 0; k < count; ++k) {
         if (ns[k] < 1 || ns[k] > HAC_MAX_BATCH_N)
             return fail(c, HAC_EINVAL, "instance %d: n=%d outside 1..%d", k, ns[k], HAC_MAX_BATCH_N);
-        if (linkages[k] < 0 || linkages[k] > 3) return fail(c, HAC_EINVAL, "instance %d: linkage %d", k, linkages[k]);
+        if (linkages[k] < 0 || linkages[k] > HAC_CENTROID)
+            return fail(c, HAC_EINVAL, "instance %d: linkage %d", k, linkages[k]);
         if (offsets[k] < 0 || out_offsets[k] < 0) return fail(c, HAC_EINVAL, "instance %d: negative offset", k);
         extent = std::max(extent, offsets[k] + (int64_t)ns[k] * ns[k]);
         rec_extent = std::max(rec_extent, out_offsets[k] + (int64_t)ns[k] - 1);

@@ -79,10 +79,11 @@ __device__ __forceinline__ float unord32(uint32_t o) {
 }
 
 // Table 1 update, fp32, fixed order, no contraction.  Coefficients are fp64
-// quotients rounded once to fp32.  Single/complete use the exact closed forms
-// min/max of the Table 1 rows (1/2, 1/2, 0, -+1/2).
+// quotients rounded once to fp32 (ai, aj, bij: the per-merge coefficients of
+// the group-average and centroid rows).  Single/complete use the exact closed
+// forms min/max of the Table 1 rows (1/2, 1/2, 0, -+1/2).
 __device__ __forceinline__ float lw_update(int link, float dki, float dkj, float dij, int ni,
-                                           int nj, int nk, float ai, float aj) {
+                                           int nj, int nk, float ai, float aj, float bij) {
     float v;
     if (link == HAC_SINGLE) {
         v = fminf(dki, dkj);
@@ -90,6 +91,10 @@ __device__ __forceinline__ float lw_update(int link, float dki, float dkj, float
         v = fmaxf(dki, dkj);
     } else if (link == HAC_AVERAGE) {
         v = __fadd_rn(__fmul_rn(ai, dki), __fmul_rn(aj, dkj));
+    } else if (link == HAC_WEIGHTED) {
+        v = __fadd_rn(__fmul_rn(0.5f, dki), __fmul_rn(0.5f, dkj));
+    } else if (link == HAC_CENTROID) {
+        v = __fadd_rn(__fadd_rn(__fmul_rn(ai, dki), __fmul_rn(aj, dkj)), __fmul_rn(bij, dij));
     } else {
         double t = (double)(ni + nj + nk);
         float wi = (float)((double)(ni + nk) / t);
@@ -708,11 +713,12 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         if (prof) st.lap(kPhRescan);
 
         // ---- Lance-Williams update of row/column i (Section 4 step 3) -----
-        float ai = 0.0f, aj = 0.0f;
-        if (link == HAC_AVERAGE) {
+        float ai = 0.0f, aj = 0.0f, bij = 0.0f;
+        if (link == HAC_AVERAGE || link == HAC_CENTROID) {
             const double sum = (double)(ni + nj);
             ai = (float)((double)ni / sum);
             aj = (float)((double)nj / sum);
+            bij = (float)(-((double)ni * (double)nj) / (sum * sum));
         }
         uint64_t q2 = kEmpty;
         uint64_t pc = kEmpty;  // this workgroup's candidates for epoch e+1
@@ -733,7 +739,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 const int k = chunk_of(lq, g, w) * 64 + lane;
                 if (k >= n || k == i || k == j || !is_live(L.amask, k)) continue;
                 const int nk = link == HAC_WARD ? (int)L.size1[k] + 1 : 1;
-                const float v = lw_update(link, a[u], bv[u], h, ni, nj, nk, ai, aj);
+                const float v = lw_update(link, a[u], bv[u], h, ni, nj, nk, ai, aj, bij);
                 if (defer) {
                     // Written through to the device's point of coherence, so
                     // that the release before the next exchange has little to

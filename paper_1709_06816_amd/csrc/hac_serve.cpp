@@ -535,7 +535,7 @@ int hac_submit(hac_server *s, const float *host_dist, int64_t ld, int32_t n, int
     if (!host_dist || !ticket) return sfail(s, HAC_EINVAL, "NULL argument");
     if (n < 1 || n > s->max_n) return sfail(s, HAC_EINVAL, "n=%d outside 1..%d", n, s->max_n);
     if (ld < n) return sfail(s, HAC_EINVAL, "ld=%lld < n=%d", (long long)ld, n);
-    if (linkage < 0 || linkage > 3) return sfail(s, HAC_EINVAL, "linkage %d", linkage);
+    if (linkage < 0 || linkage > HAC_CENTROID) return sfail(s, HAC_EINVAL, "linkage %d", linkage);
     if (s->failed != HAC_OK) return s->failed;
     if (s->quit) return sfail(s, HAC_EINVAL, "server is shutting down");
     const int g = group_for(n, s->info.lds_max);

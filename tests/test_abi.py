@@ -99,3 +99,13 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[cname + " size"] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got["%s %s" % (cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_linkage_names_match_header():
+    """The binding's linkage names map onto the hac_linkage values of
+    include/hac.h, one for each Table 1 row."""
+    with open(os.path.join(ROOT, "include", "hac.h")) as f:
+        src = f.read()
+    body = re.search(r"typedef enum \{(.*?)\} hac_linkage;", src, re.S).group(1)
+    declared = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"HAC_(\w+)\s*=\s*(\d+)", body)}
+    assert declared == hac.LINKAGES

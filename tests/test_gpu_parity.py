@@ -1,7 +1,8 @@
 """GPU parity: the HIP library, called through its C-ABI, against the CPU
 oracle on the same seeded inputs.  Merge lists must be byte-identical
-(indices, fp32 heights and sizes): single/complete are exact, average/Ward
-follow the same fixed fp32 recipe on both sides.
+(indices, fp32 heights and sizes): single/complete are exact; average,
+weighted average, centroid and Ward follow the same fixed fp32 recipe on both
+sides.
 
 At the full n=32768 RMSD-like size the oracle cannot run to the end in a
 test, so there the GPU list is checked on its first merges against the
@@ -19,7 +20,8 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-LINKS = ["single", "complete", "average", "ward"]
+# Table 1 rows; "weighted" is the Weighted Average row.
+LINKS = ["single", "complete", "average", "ward", "weighted", "centroid"]
 
 
 def _say(*a):
@@ -302,6 +304,31 @@ def test_batch_ragged_edges(ctx, torch):
         n = int(ns[k])
         exp = oracle.run_f32(m, int(links[k]))
         assert _same(res[moff[k]:moff[k] + n - 1], exp), k
+
+
+def test_batch_all_linkages(ctx, torch):
+    """One batch holding every linkage, with instances large enough for
+    groups of workgroups, on the tuned plan and on fixed plans with and
+    without groups: every instance byte-identical to the oracle."""
+    ns = np.array([2300, 2100, 700, 650, 300, 257, 130, 129, 65, 64, 33, 5, 3, 2], np.int64)
+    links = np.array([5, 4, 4, 5, 0, 1, 2, 3, 4, 5, 5, 4, 5, 4], np.int32)
+    mats = [synth.batch_instance(int(n), 6100 + k) for k, n in enumerate(ns)]
+    offs, total = synth.pack_offsets(ns)
+    packed = np.zeros(total, np.float32)
+    for k, m in enumerate(mats):
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+    t = torch.from_numpy(packed).cuda()
+    moff, _ = synth.merge_offsets(ns)
+    exps = [oracle.run_f32(m, int(links[k])) for k, m in enumerate(mats)]
+    for block, group in [(0, 0), (256, 1), (1024, 4)]:
+        _say("batch all linkages block=%d group=%d" % (block, group))
+        res, st = _batch_with_plan(ctx, torch, t, offs, ns, links, block, group)
+        if group:
+            assert st["group"] == group
+        for k in range(len(ns)):
+            n = int(ns[k])
+            got = res[moff[k]:moff[k] + n - 1]
+            assert _same(got, exps[k]), (block, group, k, n, int(links[k]), _diff(got, exps[k]))
 
 
 def _batch_with_plan(ctx, torch, t, offs, ns, links, block, group):

@@ -15,7 +15,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-LINKS = ["single", "complete", "average", "ward"]
+LINKS = ["single", "complete", "average", "ward", "weighted", "centroid"]
 
 
 def _say(*a):
@@ -72,7 +72,7 @@ def _jobs():
     jobs = []
     for k, n in enumerate(ns):
         d = synth.batch_instance(n, 5150 + k) if n > 1 else np.zeros((1, 1), np.float32)
-        jobs.append((n, LINKS[k % 4], d))
+        jobs.append((n, LINKS[k % len(LINKS)], d))
     return jobs
 
 
@@ -113,7 +113,7 @@ def test_server_mix_matches_run(ctx, torch, hac):
     synth.serve_pool(2, N, out=[p.numpy() for p in pool])
     rng = np.random.default_rng(5)
     ns = np.minimum(synth.log_uniform_int(rng, 64, N, size=count), N)
-    links = rng.integers(0, 4, size=count)
+    links = rng.integers(0, 6, size=count)
     refs = [_run_ref(ctx, torch, pool[k % 2][:int(ns[k]), :int(ns[k])].numpy(), int(links[k]))
             for k in range(count)]
     with hac.Server(ctx, budget_bytes=8 << 30, max_jobs=256, max_n=N) as srv:
