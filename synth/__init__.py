@@ -262,3 +262,45 @@ def ultrametric_matrix(n: int, seed: int) -> np.ndarray:
 
     split(list(perm))
     return d.astype(np.float32)
+
+
+def conformations(count: int, atoms: int, seed: int = BASE_SEED + 7, states: int = 64) -> np.ndarray:
+    """``count`` conformations of one chain of ``atoms`` atoms, as a
+    (count, atoms, 3) fp32 array in angstrom: the shape of the paper's input
+    before its RMSD step (chains of one sequence folded differently, Section
+    2.1; RMSD computed in parallel, Section 5.1).
+
+    Recipe: a base chain is a persistent random walk with 3.8 A steps (the
+    C-alpha spacing of a protein backbone); ``states`` folding states each add
+    a smooth displacement field to it (a sum of three random sinusoids along
+    the chain, amplitude ~ U[1, 4] A); a conformation picks a state, adds
+    isotropic noise sigma ~ U[0.2, 1.0] A per atom, and is placed by a random
+    proper rotation and a translation ~ U[-50, 50]^3 A, so that the
+    superposition matters.  Pure input generation: no RMSD arithmetic."""
+    rng = np.random.default_rng(seed)
+    step = rng.standard_normal((atoms, 3))
+    for i in range(1, atoms):  # persistence: each step leans on the previous one
+        step[i] = 0.6 * step[i - 1] + step[i]
+    step *= 3.8 / np.maximum(np.linalg.norm(step, axis=1, keepdims=True), 1e-12)
+    base = np.cumsum(step, axis=0)
+    base -= base.mean(0)
+    pos = np.arange(atoms, dtype=np.float64)[:, None]
+    fields = np.zeros((states, atoms, 3))
+    for c in range(states):
+        amp = rng.uniform(1.0, 4.0)
+        for _ in range(3):
+            freq = rng.uniform(0.01, 0.2)
+            phase = rng.uniform(0, 2 * np.pi, size=3)
+            direc = rng.standard_normal(3)
+            fields[c] += amp / 3.0 * np.sin(freq * pos + phase) * direc / np.linalg.norm(direc)
+    label = rng.integers(0, states, size=count)
+    sigma = rng.uniform(0.2, 1.0, size=count)
+    out = np.empty((count, atoms, 3), np.float32)
+    for k in range(count):
+        x = base + fields[label[k]] + sigma[k] * rng.standard_normal((atoms, 3))
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        out[k] = (x @ q.T + rng.uniform(-50, 50, size=3)).astype(np.float32)
+    return out
