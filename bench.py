@@ -321,6 +321,43 @@ def serve_leg(torch, hac, ctx, requests, warmup, rate, budget_gb, big_n):
     return res
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def rmsd_leg(torch, hac, ctx, n, atoms, reps):
+    """The input producer (hac_rmsd): the n x n superposed-RMSD matrix of n
+    conformations of ``atoms`` atoms.  Algorithmic work: the nine
+    cross-covariance sums of every pair in the strict upper triangle,
+    2 * 9 * atoms flops per pair on the fp32 matrix cores (the fp64
+    per-pair eigenvalue epilogue is not counted).  Timed with HIP events on
+    the stream the kernels run on (torch's current stream)."""
+    import synth
+    coords = torch.from_numpy(synth.conformations(n, atoms)).cuda()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ctx.rmsd(coords, out=out)  # warm-up (workspace allocation)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        ctx.rmsd(coords, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    pairs = n * (n - 1) / 2.0
+    flops = pairs * 18.0 * atoms
+    tflops = flops / (ms / 1000.0) / 1e12
+    del out, coords
+    torch.cuda.empty_cache()
+    return {"workload": "%d conformations of a %d-atom chain (64 folding states, per-atom noise, random "
+                        "placement)" % (n, atoms), "n": n, "atoms": atoms, "reps": reps, "ms": ms,
+            "pairs_per_s": pairs / (ms / 1000.0),
+            "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS,
+                         "alg_flops": flops, "kernel": "k_rmsd_tiles (with k_rmsd_prep)",
+                         "out_bytes": pairs * 4.0,
+                         "note": "fp32 32x32x2 MFMA cross-covariances, fp64 eigenvalue epilogue per pair"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +372,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--scan-n", type=int, default=8192)
+    ap.add_argument("--no-rmsd", action="store_true")
+    ap.add_argument("--rmsd-n", type=int, default=32768)
+    ap.add_argument("--rmsd-atoms", type=int, default=128)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -434,6 +474,10 @@ def main():
     if not args.no_scan:
         log("paper scan mode at n=%d" % args.scan_n)
         result["paper_scan_mode"] = scan_leg(torch, hac, ctx, args.scan_n)
+    if not args.no_rmsd:
+        log("input producer: rmsd n=%d atoms=%d" % (args.rmsd_n, args.rmsd_atoms))
+        result["input_producer"] = rmsd_leg(torch, hac, ctx, args.rmsd_n, args.rmsd_atoms, reps=5)
+        log("rmsd %.2f ms" % result["input_producer"]["ms"])
     if not args.no_batch:
         log("batch leg")
         result["batched"] = batch_leg(torch, hac, ctx, args.batch_count, 64, 4096, reps=3)

@@ -133,6 +133,35 @@ int hac_batch(hac_ctx *ctx, float *packed, const int64_t *offsets, const int32_t
               const int32_t *linkages, int32_t count, hac_merge *out,
               const int64_t *out_offsets, uint32_t flags, void *stream);
 
+/*
+ * hac_rmsd -- the input producer: the matrix of RMSDs between n conformations
+ * of one chain (the paper clusters protein conformations by such a matrix,
+ * computed by a parallel RMSD step: Section 2.1's protein example, Section
+ * 5.1).  RMSD(A, B) is the root mean square deviation of corresponding atoms
+ * after the best superposition of A onto B by a proper rotation and a
+ * translation.
+ *   coords: device pointer, n x atoms x 3 fp32 (conformation-major, then
+ *           atom, then x, y, z), caller-owned, read only.  Every coordinate
+ *           must be finite with |x| <= 2^40, otherwise HAC_EINPUT and dist
+ *           is not written.
+ *   n:      conformations, 1..HAC_MAX_N.  atoms: 1..2^20.
+ *   dist:   device pointer, n x n fp32, row-major, leading dimension n,
+ *           caller-owned.  The strict upper triangle receives RMSD(a, b)
+ *           for a < b and the diagonal 0; the lower triangle is not written
+ *           (hac_run reads only the strict upper triangle, so dist can be
+ *           passed to it directly).
+ *   flags:  0.
+ *   stream: hipStream_t to enqueue on; NULL = HIP's default stream.  The
+ *           call returns when the matrix is complete.
+ *   Arithmetic: centroids and squared norms in fp64; centred coordinates
+ *   rounded to fp32; the nine cross-covariance sums in fp32 on the matrix
+ *   cores; the largest eigenvalue of the 4 x 4 quaternion key matrix and the
+ *   RMSD in fp64, rounded once to fp32.  The device workspace (12 bytes per
+ *   atom and conformation) is kept by the context and grown on demand.
+ */
+int hac_rmsd(hac_ctx *ctx, const float *coords, int32_t n, int32_t atoms, float *dist, uint32_t flags,
+             void *stream);
+
 /* hac_sync -- wait for the context's last HAC_OUT_DEVICE call and return its status. */
 int hac_sync(hac_ctx *ctx);
 

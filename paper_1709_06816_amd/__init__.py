@@ -48,7 +48,7 @@ _STATUS_NAMES = {
 }
 
 # Symbols the library must export (one per declaration in include/hac.h).
-EXPORTS = ("hac_create", "hac_destroy", "hac_run", "hac_batch", "hac_sync", "hac_last_error",
+EXPORTS = ("hac_create", "hac_destroy", "hac_run", "hac_batch", "hac_rmsd", "hac_sync", "hac_last_error",
            "hac_set_option", "hac_get_stats", "hac_server_create", "hac_submit", "hac_poll",
            "hac_server_get_stats", "hac_server_last_error", "hac_server_destroy")
 
@@ -105,6 +105,7 @@ def load_library():
         lib.hac_destroy.argtypes = [vp]
         lib.hac_run.argtypes = [vp, vp, i32, i32, vp, u32, vp]
         lib.hac_batch.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, u32, vp]
+        lib.hac_rmsd.argtypes = [vp, vp, i32, i32, vp, u32, vp]
         lib.hac_sync.argtypes = [vp]
         lib.hac_last_error.argtypes = [vp]
         lib.hac_last_error.restype = ctypes.c_char_p
@@ -225,6 +226,26 @@ class Context:
                                       ctypes.c_void_p(optr) if optr else None, flags,
                                       ctypes.c_void_p(s) if s else None))
         return res
+
+    def rmsd(self, coords, out=None, stream=None):
+        """RMSD matrix of n conformations (hac_rmsd): ``coords`` a contiguous
+        float32 device tensor (n, atoms, 3).  Returns ``out`` (a float32
+        device tensor (n, n), allocated if not given) with the strict upper
+        triangle and the diagonal written."""
+        import torch
+        if coords.dtype != torch.float32 or coords.dim() != 3 or coords.shape[2] != 3:
+            raise ValueError("coords must be a float32 tensor (n, atoms, 3)")
+        if not coords.is_contiguous():
+            raise ValueError("coords must be contiguous")
+        n, atoms = int(coords.shape[0]), int(coords.shape[1])
+        if out is None:
+            out = torch.empty((n, n), dtype=torch.float32, device=coords.device)
+        elif tuple(out.shape) != (n, n) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor (n, n)")
+        s = _stream_of(stream)
+        self._check(self._lib.hac_rmsd(self._h, ctypes.c_void_p(_dev_ptr(coords)), n, atoms,
+                                       ctypes.c_void_p(_dev_ptr(out)), 0, ctypes.c_void_p(s) if s else None))
+        return out
 
     def batch(self, packed, offsets, ns, linkages, preserve: bool = False, out=None,
               stream=None) -> np.ndarray:

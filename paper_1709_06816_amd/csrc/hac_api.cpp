@@ -14,6 +14,7 @@
 #include "hac.h"
 #include "hac_ctx_info.h"
 #include "hac_engine.h"
+#include "hac_rmsd.h"
 
 namespace {
 
@@ -45,6 +46,8 @@ struct hac_ctx {
     size_t ws_cap = 0;
     float *dcopy = nullptr;      // HAC_PRESERVE_INPUT copy
     size_t dcopy_cap = 0;        // bytes
+    void *rmsd_ws = nullptr;     // RMSD producer: coordinate planes, norms, status
+    size_t rmsd_cap = 0;
     hac_merge *dout = nullptr;   // device merge records when the caller's out is host memory
     size_t dout_cap = 0;         // records
     void *pinned = nullptr;      // host staging (status read-back, descriptor upload)
@@ -458,12 +461,39 @@ int hac_destroy(hac_ctx *c) {
     clear_graphs(c);
     if (c->ws) (void)hipFree(c->ws);
     if (c->dcopy) (void)hipFree(c->dcopy);
+    if (c->rmsd_ws) (void)hipFree(c->rmsd_ws);
     if (c->dout) (void)hipFree(c->dout);
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
+    return HAC_OK;
+}
+
+int hac_rmsd(hac_ctx *c, const float *coords, int32_t n, int32_t atoms, float *dist, uint32_t flags, void *stream) {
+    if (!c) return HAC_EINVAL;
+    c->err.clear();
+    if (!coords || !dist) return fail(c, HAC_EINVAL, "coords or dist is NULL");
+    if (n < 1 || n > HAC_MAX_N) return fail(c, HAC_EINVAL, "n=%d outside 1..%d", n, HAC_MAX_N);
+    if (atoms < 1 || atoms > hac::kRmsdMaxAtoms)
+        return fail(c, HAC_EINVAL, "atoms=%d outside 1..%d", atoms, hac::kRmsdMaxAtoms);
+    if (flags != 0) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
+    int rc = set_device(c);
+    if (rc) return rc;
+    if (c->pending) (void)hac_sync(c);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const hac::RmsdLayout L = hac::rmsd_layout(n, atoms);
+    rc = ensure_dev(c, &c->rmsd_ws, &c->rmsd_cap, L.bytes, "the RMSD workspace");
+    if (rc) return rc;
+    rc = ensure_pinned(c, 64);
+    if (rc) return rc;
+    HIP_TRY(c, hac::launch_rmsd(coords, n, atoms, dist, c->rmsd_ws, s));
+    HIP_TRY(c, hipMemcpyAsync(c->pinned, static_cast<char *>(c->rmsd_ws) + L.status_offset, sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (*static_cast<const uint32_t *>(c->pinned) != 0u)
+        return fail(c, HAC_EINPUT, "a coordinate is not finite or exceeds 2^40 in magnitude");
     return HAC_OK;
 }
 
