@@ -16,13 +16,13 @@ constexpr int kRmsdMaxAtoms = 1 << 20;
 
 // Workspace of one call: centred coordinate planes, squared norms, status.
 struct RmsdLayout {
-    int npad = 0;            // conformations rounded up to the 64-block
-    int half = 0;            // atom pairs (padding atom for odd m)
+    int npad = 0;            // conformations rounded up to a multiple of 64
+    int quads = 0;           // groups of 4 atoms, a multiple of 8 (padding atoms zero)
     size_t planes_bytes = 0;
     size_t sq_offset = 0;
     size_t status_offset = 0;
     size_t bytes = 0;        // whole workspace
-    int64_t blocks = 0;      // pair blocks on or above the diagonal
+    int64_t blocks = 0;      // workgroups: whole super-blocks on or above the diagonal
 };
 
 RmsdLayout rmsd_layout(int n, int atoms);

@@ -8,20 +8,28 @@
 //                 coordinates rounded to fp32 into three coordinate planes
 //                 laid out for the matrix cores, squared norm (fp64 sum of the
 //                 rounded coordinates), input check.
-//   k_rmsd_tiles  one 256-thread workgroup per 64 x 64 block of pairs on or
-//                 above the diagonal; each wave owns a 32 x 32 pair tile and
+//   k_rmsd_tiles  one 256-thread workgroup per 32 x 32 block of pairs on or
+//                 above the diagonal; each wave owns a 16 x 16 pair tile and
 //                 accumulates the nine cross-covariance sums
 //                 M_pq(s, t) = sum_i a_p(s, i) * a_q(t, i) with nine fp32
-//                 32x32x2 MFMA accumulators, two atoms per instruction; lane
-//                 l of every accumulator holds the same 16 pairs, so each lane
-//                 finishes its pairs in registers (hac_qcp.h, fp64) and
-//                 writes the strict upper triangle (diagonal 0).
+//                 16x16x4 MFMA accumulators (four registers each), four atoms
+//                 per instruction; lane l of every accumulator holds the same
+//                 4 pairs, so each lane finishes its pairs in registers
+//                 (hac_qcp.h, fp64) and writes the strict upper triangle
+//                 (diagonal 0).  The small accumulator footprint leaves room
+//                 for several waves per SIMD, so one wave's fp64 epilogue
+//                 runs beside another's matrix instructions.
 //
-// Plane layout (device workspace): planes[((p * half + k) * npad + s) * 2 + h]
-// is coordinate p of atom 2k + h of conformation s (zero for the padding atom
-// of odd m and for the padding conformations s >= n), npad = n rounded up to
-// 64.  For the MFMA operand, lanes 0-31 read atom 2k and lanes 32-63 atom
-// 2k + 1 of 32 consecutive conformations: 256 contiguous bytes per plane.
+// Coordinate layout (device workspace): conformations in tiles of 16, atoms
+// in groups of 4 (one MFMA's k), groups in chunks of 8.  Within tile T and
+// chunk C, coordinate p of atom h of group c = 4 g + j of conformation r of
+// the tile is at
+//     coords[(T * chunks + C) * 1536 + (((p * 2 + g) * 4 + h) * 16 + r) * 4 + j]
+// (zero for padding atoms and padding conformations).  MFMA lane l = 16 h + r
+// needs, for groups 4 g .. 4 g + 3, the four floats j = 0..3 at one 16-byte
+// aligned address: one 16-byte load per (p, g), consecutive lanes at
+// consecutive addresses (1 KiB per wave and load), six loads per operand and
+// chunk at immediate offsets from one pointer per lane.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -31,9 +39,16 @@
 namespace hac {
 namespace {
 
-typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kPairBlock = 64;  // conformations per workgroup block side
+constexpr int kPad = 64;        // conformations are padded to a multiple of this
+constexpr int kPairBlock = 32;  // conformations per workgroup block side
+constexpr int kGroup = 4;       // atoms per matrix instruction
+constexpr int kSuper = 8;       // pair blocks per super-block side (L2 reuse)
+constexpr int kChunk = 8;       // atom groups per chunk; groups are padded to a multiple of it
+constexpr int kTile = 16;       // conformations per tile (an MFMA operand's rows)
+constexpr int kBlockFloats = kTile * kGroup;            // one (p, c) block
+constexpr int kChunkFloats = 3 * kChunk * kBlockFloats;  // one chunk of a tile
 constexpr float kMaxCoord = (float)kRmsdMaxCoord;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -46,19 +61,28 @@ __global__ void k_rmsd_clear(uint32_t *status) {
     if (threadIdx.x == 0) *status = 0u;
 }
 
+// Offset of coordinate 0 of atom i of conformation s; coordinate p is at
+// + p * kPlaneStep.
+__device__ __forceinline__ size_t coord_at(int i, int s, int chunks) {
+    const int k = i / kGroup, c = k % kChunk;
+    return ((size_t)(s / kTile) * chunks + k / kChunk) * kChunkFloats +
+           ((((c / 4) * kGroup + i % kGroup) * kTile + s % kTile) * 4 + c % 4);
+}
+constexpr int kPlaneStep = kChunk * kBlockFloats;  // between coordinates p and p + 1
+
 __global__ __launch_bounds__(256) void k_rmsd_prep(const float *__restrict__ xyz, int n, int npad, int atoms,
-                                                   int half, float *__restrict__ planes, double *__restrict__ sq,
+                                                   int quads, float *__restrict__ planes, double *__restrict__ sq,
                                                    uint32_t *__restrict__ status) {
     const int lane = threadIdx.x & 63;
     const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (s >= npad) return;
-    const size_t pstride = (size_t)half * npad * 2;
+    const int chunks = quads / kChunk;
     if (s >= n) {  // padding conformation: zeros
-        for (int i = lane; i < 2 * half; i += 64) {
-            const size_t o = ((size_t)(i >> 1) * npad + s) * 2 + (i & 1);
+        for (int i = lane; i < kGroup * quads; i += 64) {
+            const size_t o = coord_at(i, s, chunks);
             planes[o] = 0.0f;
-            planes[o + pstride] = 0.0f;
-            planes[o + 2 * pstride] = 0.0f;
+            planes[o + kPlaneStep] = 0.0f;
+            planes[o + 2 * kPlaneStep] = 0.0f;
         }
         if (lane == 0) sq[s] = 0.0;
         return;
@@ -81,7 +105,7 @@ __global__ __launch_bounds__(256) void k_rmsd_prep(const float *__restrict__ xyz
     c1 = wave_sum(c1) / atoms;
     c2 = wave_sum(c2) / atoms;
     double g = 0.0;
-    for (int i = lane; i < 2 * half; i += 64) {
+    for (int i = lane; i < kGroup * quads; i += 64) {
         float u = 0.0f, v = 0.0f, w = 0.0f;
         if (i < atoms) {
             u = (float)((double)x[3 * i] - c0);
@@ -89,10 +113,10 @@ __global__ __launch_bounds__(256) void k_rmsd_prep(const float *__restrict__ xyz
             w = (float)((double)x[3 * i + 2] - c2);
             g += (double)u * u + (double)v * v + (double)w * w;
         }
-        const size_t o = ((size_t)(i >> 1) * npad + s) * 2 + (i & 1);
+        const size_t o = coord_at(i, s, chunks);
         planes[o] = u;
-        planes[o + pstride] = v;
-        planes[o + 2 * pstride] = w;
+        planes[o + kPlaneStep] = v;
+        planes[o + 2 * kPlaneStep] = w;
     }
     g = wave_sum(g);
     if (lane == 0) sq[s] = g;
@@ -100,78 +124,92 @@ __global__ __launch_bounds__(256) void k_rmsd_prep(const float *__restrict__ xyz
 
 __global__ __launch_bounds__(256) void k_rmsd_tiles(const float *__restrict__ planes, const double *__restrict__ sq,
                                                     const uint32_t *__restrict__ status, int n, int npad, int atoms,
-                                                    int half, int64_t nblocks, float *__restrict__ out, int64_t ld) {
+                                                    int quads, int64_t nblocks, float *__restrict__ out, int64_t ld) {
     if (*status != 0u) return;  // rejected input: the output stays untouched
 
     // Blocks are handed to the 8 XCDs round-robin; renumber them so that each
-    // XCD takes one contiguous run of pair blocks (shared conformations stay
-    // in that XCD's L2).
+    // XCD takes one contiguous run of pair blocks.
     const int64_t bid = blockIdx.x;
     const int64_t q = nblocks / 8, r = nblocks % 8;
     const int64_t xcd = bid % 8, j = bid / 8;
     const int64_t idx = xcd * q + (xcd < r ? xcd : r) + j;
-    // Column-major enumeration of the upper triangle: idx = bt (bt + 1) / 2 + bs.
-    int64_t bt = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
-    while (bt * (bt + 1) / 2 > idx) --bt;
-    while ((bt + 1) * (bt + 2) / 2 <= idx) ++bt;
-    const int64_t bs = idx - bt * (bt + 1) / 2;
+    // The run walks super-blocks of kSuper x kSuper pair blocks on or above
+    // the diagonal (column-major: sb = st (st + 1) / 2 + ss), each one whole:
+    // its 2 kSuper conformation tiles stay in the XCD's L2 while its
+    // kSuper^2 blocks use them.  Blocks below the diagonal or past the last
+    // conformation exit at once.
+    const int64_t sb = idx / (kSuper * kSuper), within = idx % (kSuper * kSuper);
+    int64_t st = (int64_t)((sqrt(8.0 * (double)sb + 1.0) - 1.0) * 0.5);
+    while (st * (st + 1) / 2 > sb) --st;
+    while ((st + 1) * (st + 2) / 2 <= sb) ++st;
+    const int64_t ss = sb - st * (st + 1) / 2;
+    const int64_t bs = ss * kSuper + within / kSuper, bt = st * kSuper + within % kSuper;
+    if (bs > bt) return;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int s0 = (int)bs * kPairBlock + (wave >> 1) * 32;
-    const int t0 = (int)bt * kPairBlock + (wave & 1) * 32;
-    if (s0 >= n || t0 >= n || s0 > t0 + 31) return;  // no pair of this tile is wanted
+    const int s0 = (int)bs * kPairBlock + (wave >> 1) * 16;
+    const int t0 = (int)bt * kPairBlock + (wave & 1) * 16;
+    if (s0 >= n || t0 >= n || s0 > t0 + 15) return;  // no pair of this tile is wanted
 
-    const int rr = lane & 31, hh = lane >> 5;
-    const size_t pstride = (size_t)half * npad * 2, kstride = (size_t)npad * 2;
-    const float *pa = planes + (size_t)(s0 + rr) * 2 + hh;
-    const float *pb = planes + (size_t)(t0 + rr) * 2 + hh;
-    v16f acc[9];
+    const int rr = lane & 15, hh = lane >> 4;
+    const int chunks = quads / kChunk;
+    const float *pa = planes + (size_t)(s0 / kTile) * chunks * kChunkFloats + lane * 4;
+    const float *pb = planes + (size_t)(t0 / kTile) * chunks * kChunkFloats + lane * 4;
+    v4f acc[9];
 #pragma unroll
-    for (int u = 0; u < 9; ++u) acc[u] = v16f{0.0f};
-    // Atom pairs in chunks of kChunk: the next chunk's loads are issued
-    // before the current chunk's 9 * kChunk matrix instructions.
-    constexpr int kChunk = 4;
-    float ca[3][kChunk], cb[3][kChunk], na[3][kChunk], nb[3][kChunk];
-    auto load = [&](int k0, float (&xa)[3][kChunk], float (&xb)[3][kChunk]) {
+    for (int u = 0; u < 9; ++u) acc[u] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    // Two register buffers of kChunk atom groups, used in turn: the loads of
+    // one are in flight while the matrix instructions consume the other (no
+    // copies between them, so the wait before a chunk leaves the other
+    // chunk's loads outstanding).  quads is a multiple of kChunk.
+    float a0[3][kChunk], b0[3][kChunk], a1[3][kChunk], b1[3][kChunk];
+    auto load = [&](int chunk, float (&xa)[3][kChunk], float (&xb)[3][kChunk]) {
+        const float *qa = pa + (size_t)chunk * kChunkFloats;
+        const float *qb = pb + (size_t)chunk * kChunkFloats;
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-            const bool in = k0 + c < half;
-            const size_t o = (size_t)(in ? k0 + c : 0) * kstride;
+        for (int p = 0; p < 3; ++p) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                xa[p][c] = in ? pa[o + p * pstride] : 0.0f;
-                xb[p][c] = in ? pb[o + p * pstride] : 0.0f;
+            for (int g = 0; g < kChunk / 4; ++g) {
+                const float4 va = *reinterpret_cast<const float4 *>(qa + (p * 2 + g) * 256);
+                const float4 vb = *reinterpret_cast<const float4 *>(qb + (p * 2 + g) * 256);
+                xa[p][4 * g] = va.x;
+                xa[p][4 * g + 1] = va.y;
+                xa[p][4 * g + 2] = va.z;
+                xa[p][4 * g + 3] = va.w;
+                xb[p][4 * g] = vb.x;
+                xb[p][4 * g + 1] = vb.y;
+                xb[p][4 * g + 2] = vb.z;
+                xb[p][4 * g + 3] = vb.w;
             }
         }
     };
-    load(0, ca, cb);
-    for (int k0 = 0; k0 < half; k0 += kChunk) {
-        if (k0 + kChunk < half) load(k0 + kChunk, na, nb);
+    auto mma = [&](const float (&xa)[3][kChunk], const float (&xb)[3][kChunk]) {
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) {
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
 #pragma unroll
                 for (int qq = 0; qq < 3; ++qq)
-                    acc[3 * p + qq] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[p][c], cb[qq][c], acc[3 * p + qq], 0, 0, 0);
+                    acc[3 * p + qq] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[p][c], xb[qq][c], acc[3 * p + qq], 0, 0, 0);
             }
         }
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-#pragma unroll
-            for (int c = 0; c < kChunk; ++c) {
-                ca[p][c] = na[p][c];
-                cb[p][c] = nb[p][c];
-            }
-        }
+    };
+    load(0, a0, b0);
+    for (int ch = 0; ch < chunks; ch += 2) {
+        const bool second = ch + 1 < chunks;
+        if (second) load(ch + 1, a1, b1);
+        mma(a0, b0);
+        if (!second) break;
+        if (ch + 2 < chunks) load(ch + 2, a0, b0);
+        mma(a1, b1);
     }
-    // Accumulator element e of lane l: row 8 (e / 4) + 4 (l / 32) + e % 4 of
-    // the tile (conformation s), column l % 32 (conformation t).
+    // Accumulator element e of lane l: row 4 (l / 16) + e of the tile
+    // (conformation s), column l % 16 (conformation t).
     const int t = t0 + rr;
     const double gt = t < n ? sq[t] : 0.0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int s = s0 + 8 * (e >> 2) + 4 * hh + (e & 3);
+    for (int e = 0; e < 4; ++e) {
+        const int s = s0 + 4 * hh + e;
         if (s < n && t < n && s <= t) {
             float v = 0.0f;
             if (s != t) {
@@ -188,14 +226,15 @@ __global__ __launch_bounds__(256) void k_rmsd_tiles(const float *__restrict__ pl
 
 RmsdLayout rmsd_layout(int n, int atoms) {
     RmsdLayout L;
-    L.npad = (n + kPairBlock - 1) / kPairBlock * kPairBlock;
-    L.half = (atoms + 1) / 2;
-    L.planes_bytes = (size_t)3 * L.half * L.npad * 2 * sizeof(float);
+    L.npad = (n + kPad - 1) / kPad * kPad;
+    L.quads = ((atoms + kGroup - 1) / kGroup + kChunk - 1) / kChunk * kChunk;
+    L.planes_bytes = (size_t)3 * L.quads * L.npad * kGroup * sizeof(float);
     L.sq_offset = L.planes_bytes;
     L.status_offset = L.sq_offset + (size_t)L.npad * sizeof(double);
     L.bytes = L.status_offset + 256;
     const int64_t side = L.npad / kPairBlock;
-    L.blocks = side * (side + 1) / 2;
+    const int64_t supers = (side + kSuper - 1) / kSuper;
+    L.blocks = supers * (supers + 1) / 2 * kSuper * kSuper;
     return L;
 }
 
@@ -209,11 +248,11 @@ hipError_t launch_rmsd(const float *xyz, int n, int atoms, float *out, void *ws,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rmsd_prep, dim3((unsigned)(L.npad / 4)), dim3(256), 0, stream, xyz, n, L.npad, atoms,
-                       L.half, planes, sq, status);
+                       L.quads, planes, sq, status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rmsd_tiles, dim3((unsigned)L.blocks), dim3(256), 0, stream, planes, sq, status, n, L.npad,
-                       atoms, L.half, L.blocks, out, (int64_t)n);
+                       atoms, L.quads, L.blocks, out, (int64_t)n);
     return hipGetLastError();
 }
 
