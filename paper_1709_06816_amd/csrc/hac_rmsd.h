@@ -17,7 +17,7 @@ constexpr int kRmsdMaxAtoms = 1 << 20;
 // Workspace of one call: centred coordinate planes, squared norms, status.
 struct RmsdLayout {
     int npad = 0;            // conformations rounded up to a multiple of 64
-    int quads = 0;           // groups of 4 atoms, a multiple of 8 (padding atoms zero)
+    int quads = 0;           // groups of 4 atoms, a multiple of the chunk (padding atoms zero)
     size_t planes_bytes = 0;
     size_t sq_offset = 0;
     size_t status_offset = 0;
