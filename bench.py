@@ -355,7 +355,23 @@ def rmsd_leg(torch, hac, ctx, n, atoms, reps):
                          "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS,
                          "alg_flops": flops, "kernel": "k_rmsd_tiles (with k_rmsd_prep)",
                          "out_bytes": pairs * 4.0,
-                         "note": "fp32 32x32x2 MFMA cross-covariances, fp64 eigenvalue epilogue per pair"}}
+                         "note": "fp32 16x16x4 MFMA cross-covariances, fp64 eigenvalue epilogue per pair"}}
+
+
+def rmsd_cpu_baseline(n, atoms, pairs):
+    """The RMSD oracle (fp64 Kabsch, numpy) on a bounded sample of pairs of
+    the same conformations, as pairs per second."""
+    import synth
+    from oracle import rmsd as rmsd_oracle
+    coords = synth.conformations(n, atoms)
+    rng = np.random.default_rng(0)
+    rows = rng.integers(0, n, size=pairs)
+    cols = rng.integers(0, n, size=pairs)
+    t0 = time.perf_counter()
+    rmsd_oracle.rmsd_pairs(coords, rows, cols)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pairs/s", "kind": "oracle", "cores": 1,
+            "sample": "%d random pairs of the same %d conformations (%.1f s)" % (pairs, n, dt)}
 
 
 def main():
@@ -487,6 +503,9 @@ def main():
         log("serving leg")
         result["serving"] = serve_leg(torch, hac, ctx, args.serve_requests, args.serve_warmup,
                                       args.serve_rate, args.serve_budget_gb, args.serve_big_n)
+    if not args.no_cpu and "input_producer" in result:
+        log("cpu baseline of the input producer")
+        result["input_producer"]["cpu_baseline"] = rmsd_cpu_baseline(args.rmsd_n, args.rmsd_atoms, 200000)
     if not args.no_cpu:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(d, link, n, args.cpu_budget, merges)
