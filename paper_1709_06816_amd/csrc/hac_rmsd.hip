@@ -5,9 +5,9 @@
 //
 // Two kernels:
 //   k_rmsd_prep   one wave per conformation: centroid (fp64), centred
-//                 coordinates rounded to fp32 into three coordinate planes
-//                 laid out for the matrix cores, squared norm (fp64 sum of the
-//                 rounded coordinates), input check.
+//                 coordinates rounded to fp32 into the tiled layout below,
+//                 squared norm (fp64 sum of the rounded coordinates), input
+//                 check.
 //   k_rmsd_tiles  one 256-thread workgroup per 32 x 32 block of pairs on or
 //                 above the diagonal; each wave owns a 16 x 16 pair tile and
 //                 accumulates the nine cross-covariance sums
@@ -48,6 +48,7 @@ constexpr int kSuper = 8;       // pair blocks per super-block side (L2 reuse)
 constexpr int kChunk = 4;       // atom groups per chunk; groups are padded to a multiple of it
 constexpr int kTile = 16;       // conformations per tile (an MFMA operand's rows)
 constexpr int kBlockFloats = kTile * kGroup;            // one (p, c) block
+static_assert(kChunk % 4 == 0, "a lane loads four atom groups at once");
 constexpr int kChunkFloats = 3 * kChunk * kBlockFloats;  // one chunk of a tile
 constexpr float kMaxCoord = (float)kRmsdMaxCoord;
 
