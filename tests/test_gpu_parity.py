@@ -426,7 +426,7 @@ def test_batch_graph_replays(ctx, torch):
 
 def test_batch_config_sample_vs_oracle(ctx, torch):
     """The 1024-instance batch configuration's first 256 instances (same seeds
-    and size law, n log-uniform on [64, 4096], all four linkages) in one
+    and size law, n log-uniform on [64, 4096], single, complete, average and Ward) in one
     launch with the default (tuned) plan: every instance with n <= 1536 and a
     sample of the larger ones byte-identical to the oracle, run on host
     threads in parallel."""
