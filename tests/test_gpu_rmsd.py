@@ -186,3 +186,32 @@ def test_full_size_sampled(ctx, torch):
     upper = torch.triu(d, 1)
     assert bool(torch.isfinite(upper).all())
     _say("full size: worst error / bound %.3g, max rmsd %.3f" % (np.max(err / bound), float(upper.max())))
+
+
+def test_maximum_size_sampled(ctx, torch):
+    """n = HAC_MAX_N = 65536 conformations (a 17 GB matrix, 2.1 M
+    workgroups) of 32 atoms: sampled pairs including the last rows and
+    columns against the oracle, and a sample of the diagonal."""
+    import paper_1709_06816_amd as hac
+    n, m = hac.MAX_N, 32
+    coords = synth.conformations(n, m, seed=4242)
+    _say("maximum size: producing")
+    t = torch.from_numpy(coords).cuda()
+    d = ctx.rmsd(t)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    lo = rng.integers(0, n - 1, size=1500)
+    hi = rng.integers(0, n, size=1500)
+    lo[:3] = [0, n - 2, 65535 - 16]
+    hi[:3] = [n - 1, n - 1, n - 1]
+    keep = lo < hi
+    lo, hi = lo[keep], hi[keep]
+    got = d[torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()].cpu().numpy().astype(np.float64)
+    ref = R.rmsd_pairs(coords, lo, hi)
+    err = np.abs(got ** 2 - ref ** 2)
+    bound = _bound(_norms(coords), lo, hi, ref, m)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    diag = torch.from_numpy(rng.integers(0, n, size=200)).cuda()
+    assert bool(torch.all(d[diag, diag] == 0))
+    del d, t
+    torch.cuda.empty_cache()
