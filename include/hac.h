@@ -158,6 +158,9 @@ int hac_batch(hac_ctx *ctx, float *packed, const int64_t *offsets, const int32_t
  *   cores; the largest eigenvalue of the 4 x 4 quaternion key matrix and the
  *   RMSD in fp64, rounded once to fp32.  The device workspace (12 bytes per
  *   atom and conformation) is kept by the context and grown on demand.
+ *   Errors: HAC_EINVAL (NULL pointer, n or atoms out of range, flags != 0),
+ *   HAC_EINPUT (a coordinate rejected; dist untouched), HAC_ENOMEM (the
+ *   workspace could not be allocated), HAC_EDEVICE (a HIP call failed).
  */
 int hac_rmsd(hac_ctx *ctx, const float *coords, int32_t n, int32_t atoms, float *dist, uint32_t flags,
              void *stream);
