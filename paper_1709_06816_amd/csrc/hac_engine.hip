@@ -107,25 +107,29 @@ __device__ __forceinline__ float lw_update(int link, float dki, float dkj, float
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
-// Matrix loads of the merge loop that may see entries another workgroup of
-// the group wrote inside the same launch.  When the set-up (mirror, copy-in)
-// runs in the same kernel as the merges and several workgroups share an
-// instance, these are device-scope loads (coh = true): plain loads were
-// measured to return stale entries there despite the exchange's
-// release/acquire.  The single-instance path, whose set-up is a separate
-// kernel, and workgroups alone on an instance use plain loads.
-__device__ __forceinline__ float ld_f32(const float *p, bool coh) {
-    return coh ? __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT))
-               : *p;
-}
-__device__ __forceinline__ float4 ld_f32x4(const float *p, bool coh) {
-    if (!coh) return *reinterpret_cast<const float4 *>(p);
-    const unsigned long long *q = reinterpret_cast<const unsigned long long *>(p);
-    const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return make_float4(__uint_as_float((uint32_t)a), __uint_as_float((uint32_t)(a >> 32)),
-                       __uint_as_float((uint32_t)b), __uint_as_float((uint32_t)(b >> 32)));
+// Workgroup barrier after which the global stores of every wave of the
+// workgroup are complete (acknowledged by this XCD's L2).
+//
+// Publishing to other workgroups works like this: thread 0 issues an
+// agent-scope release fence and then stores the exchange slot; a reader that
+// sees the slot takes an agent-scope acquire.  On gfx950 the release is
+// "write back this XCD's L2, then wait for my own wave's memory operations",
+// and a plain workgroup barrier waits for no global store at all (each wave
+// counts its own stores, and a workgroup-scope release needs no such wait
+// when all waves share one CU).  So a store issued by another wave just
+// before the barrier can still be in flight when thread 0 writes back the
+// L2 and publishes: it then lands in the L2 as a dirty line after the write
+// back, and a reader on another XCD, whose acquire only invalidates its own
+// caches, fetches the old value from memory.  Entries written in one merge
+// and read by another workgroup in the next (the column half of the update,
+// the mirror of the set-up, a served job's copy-in) were exposed to exactly
+// this, most often in the last merges, where the update is short and the
+// stores are issued right before the barrier.  Making every wave wait for its
+// own stores first closes the window: after this barrier, thread 0's release
+// covers the writes of the whole workgroup.
+__device__ __forceinline__ void barrier_stores_done() {
+    __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): this wave's stores are acknowledged
+    __syncthreads();
 }
 
 // Wave-wide reductions from the ROCm device library (DPP lane moves, no LDS
@@ -342,8 +346,10 @@ __device__ bool get_slot(const uint64_t *s, uint64_t gen, uint64_t &p1, uint64_t
 // Publish this workgroup's candidates of epoch e (s_acc[e&1][0..1]), wait for
 // the rest of the group, and leave the group-wide minima in s_acc[e&1][2..3]
 // (Section 5.3 steps 2-4: every processor ends up with the same global
-// minimum).  Ends with a barrier.  Returns false if the wait was abandoned;
-// the decision is the same for every thread.
+// minimum).  The caller's last barrier before the call must be
+// barrier_stores_done(), so that the release below covers every wave's
+// stores.  Ends with a barrier.  Returns false if the wait was abandoned; the
+// decision is the same for every thread.
 template <int B>
 __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Control *ctl,
                                uint64_t timeout) {
@@ -352,8 +358,9 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
     uint64_t *base = I.slots + (size_t)b * (g + 1) * kSlotStride;
     if (threadIdx.x == 0) {
         s_fail = 0;
-        // Everything this workgroup wrote before the last barrier becomes
-        // visible to whoever observes the slot.
+        // Everything this workgroup wrote before the last barrier (complete,
+        // see barrier_stores_done) becomes visible to whoever observes the
+        // slot.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         put_slot(base + (size_t)w * kSlotStride, s_acc[b][0], s_acc[b][1], gen);
     }
@@ -428,7 +435,7 @@ __device__ void init_masks(const Lds &L, int n) {
 // waves).  Returns the number of segments.  Waves below WV0 only count.
 template <int B, int WV0, int U = seg_unroll<B>()>
 __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_t *amask, int skip, int base,
-                        uint64_t *acc, unsigned long long &elems, bool coh) {
+                        uint64_t *acc, unsigned long long &elems) {
     constexpr int W = B / 64 - WV0;
     static_assert(W >= 1, "no wave left to rescan");
     const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6) - WV0;
@@ -445,7 +452,7 @@ __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int q = q0 + sg * 64 * U + u * 64 + lane;
-                x[u] = q < nq ? ld_f32x4(row + 4 * q, coh) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                x[u] = q < nq ? *reinterpret_cast<const float4 *>(row + 4 * q) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
             uint64_t best = kEmpty;
 #pragma unroll
@@ -474,7 +481,7 @@ __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int l = l0 + sg * 64 * U + u * 64 + lane;
-                x[u] = l < n ? ld_f32(row + l, coh) : 0.0f;
+                x[u] = l < n ? row[l] : 0.0f;
             }
             uint64_t best = kEmpty;
 #pragma unroll
@@ -498,11 +505,11 @@ __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_
 // needed per row.
 template <int B>
 __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, const Lds &L,
-                            uint32_t nresc, int skip, unsigned long long &elems, bool coh) {
+                            uint32_t nresc, int skip, unsigned long long &elems) {
     int base = 0;
     for (uint32_t r = 0; r < nresc; ++r) {
         const int li = L.rlist[r];
-        base += scan_row<B, 0>(D, n, row_of_local(li, g, w), L.amask, skip, base, &L.cache[li], elems, coh);
+        base += scan_row<B, 0>(D, n, row_of_local(li, g, w), L.amask, skip, base, &L.cache[li], elems);
     }
 }
 
@@ -555,7 +562,7 @@ enum : int { kLoopCached = 0, kLoopDefer = 1, kLoopScan = 2 };
 
 template <int B, int kMode>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
-                           uint64_t timeout, Stats &st, uint32_t epoch0, bool coh) {
+                           uint64_t timeout, Stats &st, uint32_t epoch0) {
     constexpr int W = B / 64;
     constexpr int U = upd_batch<B>();
     constexpr bool scan = kMode == kLoopScan, defer = kMode == kLoopDefer;
@@ -576,7 +583,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     // the second exchange of every merge (scan mode).
     uint32_t e = epoch0;
     fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(e + 1) & 1][0]);
-    __syncthreads();  // later candidates are folded inside the update loop
+    barrier_stores_done();  // later candidates are folded inside the update loop
     int i_prev = -1;
     for (int s = 0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
@@ -587,7 +594,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             // barrier of the previous merge; clear them for epoch e+1.
             if (tid == 0)
                 for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;
-            __syncthreads();
+            barrier_stores_done();
             if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout)) return;
         } else {
             // The candidates were folded during the last update (and are
@@ -624,7 +631,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             }
             __syncthreads();
             const uint32_t nf = s_nresc;
-            if (nf) rescan_rows<B>(D, n, g, w, L, nf, -1, st.rescan_elems, coh);
+            if (nf) rescan_rows<B>(D, n, g, w, L, nf, -1, st.rescan_elems);
             __syncthreads();
             if (tid == 0) {
                 st.rescans += nf;
@@ -636,7 +643,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             ++e;
             b = e & 1;
             fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b][0]);
-            __syncthreads();
+            barrier_stores_done();
             if (g > 1) {
                 if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
                 win = s_acc[b][2];
@@ -675,8 +682,8 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         for (int u = 0; u < U; ++u) {
             const int lq = wv + u * W;
             const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-            a[u] = k < n ? ld_f32(Di + k, coh) : 0.0f;
-            bv[u] = k < n ? ld_f32(Dj + k, coh) : 0.0f;
+            a[u] = k < n ? Di[k] : 0.0f;
+            bv[u] = k < n ? Dj[k] : 0.0f;
         }
         // ---- retire j (Section 5.3 step 6); queue rows whose partner is i or j
         if (tid == 0) {
@@ -707,7 +714,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         if (prof) st.lap(kPhUpdate);
         const uint32_t nresc = defer ? 0u : s_nresc;
         if (nresc) {
-            rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems, coh);
+            rescan_rows<B>(D, n, g, w, L, nresc, i, st.rescan_elems);
             if (!scan) __syncthreads();  // rescanned entries are final before the update folds them
         }
         if (prof) st.lap(kPhRescan);
@@ -728,8 +735,8 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 for (int u = 0; u < U; ++u) {
                     const int lq = lq0 + u * W;
                     const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-                    a[u] = k < n ? ld_f32(Di + k, coh) : 0.0f;
-                    bv[u] = k < n ? ld_f32(Dj + k, coh) : 0.0f;
+                    a[u] = k < n ? Di[k] : 0.0f;
+                    bv[u] = k < n ? Dj[k] : 0.0f;
                 }
             }
 #pragma unroll
@@ -783,7 +790,9 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         }
         lds_min(&s_acc[b ^ 1][1], q2);  // row i's candidates for epoch e+1
         if (!scan) lds_min(&s_acc[b ^ 1][0], pc);
-        __syncthreads();
+        // The update's stores (both halves) are complete before the next
+        // exchange publishes them.
+        barrier_stores_done();
         // Cluster i grows; every thread has read size1[i] and size1[j] for
         // this merge, and nothing reads them again before the next one.
         if (tid == 0) {
@@ -798,7 +807,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             // live upper part of all its rows for the next argmin ---------
             if (tid == 0)
                 for (int q = 0; q < 4; ++q) s_acc[b][q] = s_acc[b ^ 1][q] = kEmpty;
-            __syncthreads();
+            barrier_stores_done();
             // Every workgroup's updated entries are in place (epoch e+1).
             ++e;
             b = e & 1;
@@ -810,7 +819,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             }
             __syncthreads();
             const uint32_t nscan = s_nresc;
-            rescan_rows<B>(D, n, g, w, L, nscan, -1, st.rescan_elems, coh);
+            rescan_rows<B>(D, n, g, w, L, nscan, -1, st.rescan_elems);
             __syncthreads();
             if (tid == 0) {
                 st.rescans += nscan;
@@ -879,7 +888,7 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
         L.cache[li] = v == kEmpty ? kEmptyRow : v;
     }
     __syncthreads();
-    merge_loop<B, kMode>(I, g, w, L, ctl, timeout, st, 0u, false);
+    merge_loop<B, kMode>(I, g, w, L, ctl, timeout, st, 0u);
     flush_stats<B>(ctl, st);
 }
 
@@ -913,7 +922,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
         // which every thread reads the final status word.
         const uint32_t e = epoch_base + 1u;
         if (threadIdx.x == 0) s_acc[e & 1][0] = s_acc[e & 1][1] = s_acc[e & 1][2] = s_acc[e & 1][3] = kEmpty;
-        __syncthreads();
+        barrier_stores_done();  // the mirror (and a served job's copy-in) stores are complete
         if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
         epoch0 = e;
         if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
@@ -922,7 +931,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     }
     init_masks<B>(L, n);  // size1 shares space with the tile
     __syncthreads();
-    merge_loop<B, kLoopCached>(I, g, w, L, ctl, timeout, st, epoch0, g > 1);
+    merge_loop<B, kLoopCached>(I, g, w, L, ctl, timeout, st, epoch0);
 }
 
 // Batch: the first `ngroups` entries of `order` are run by fixed groups of
@@ -1023,9 +1032,10 @@ __device__ bool serve_claim(ServeHost *host, const ServeEntry *ring, uint32_t ca
             }
             __builtin_amdgcn_s_sleep(8);
         } else {
-            // ~14 us between polls: a crowd of idle workgroups hammering the
-            // queue words was measured to disturb the jobs running beside
-            // them (wrong merge lists in multi-workgroup jobs).
+            // ~14 us between polls: a crowd of idle workgroups polling the
+            // queue words (and trying for the token) every microsecond only
+            // adds memory traffic beside the running jobs; a claim waits at
+            // most this long.  Results do not depend on the interval.
             for (int z = 0; z < 4; ++z) __builtin_amdgcn_s_sleep(127);
         }
         // Safety net: the host stops an idle kernel long before this; if it
@@ -1111,7 +1121,11 @@ __global__ __launch_bounds__(B) void k_serve(ServeHost *host, const ServeEntry *
             __syncthreads();
             batch_instance<B>(e.inst, e.g, e.rank, smem, ctl, timeout, st);
         }
-        __syncthreads();
+        // Every wave's stores to the job's matrix are complete before thread
+        // 0's release below: the arena region is reused by later jobs, which
+        // may run on other XCDs, so no dirty line of this job may be left
+        // behind in this XCD's L2 to be written back over them.
+        barrier_stores_done();
         uint32_t *words = e.inst.status;  // [0] status, [1] members done
         if (threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
@@ -1147,7 +1161,7 @@ __global__ __launch_bounds__(B) void k_serve(ServeHost *host, const ServeEntry *
                         __hip_atomic_store(e.inst.slots + q, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-            __syncthreads();
+            barrier_stores_done();  // the cleared slots are in place before the job slot is handed back
             if (threadIdx.x == 0) {
                 __hip_atomic_store(words, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(words + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -6,8 +6,10 @@ GPU library (product side) consume what it produces.
 
 Every matrix is fp32, n x n, row-major, zero diagonal.  Only the strict upper
 triangle is meaningful to the algorithm (Section 5.2: a distance matrix needs
-only its upper or lower half); the lower triangle produced here is the mirror
-up to rounding of the Gram-matrix formula and is ignored by every consumer.
+only its upper or lower half); the lower triangle produced here is its exact
+mirror and is ignored by every consumer.  The fp64 arithmetic that turns
+points into distances runs in a small C helper (_gen.c) with every sum in a
+fixed order, so a seeded matrix is the same bytes on every host.
 
 Workload recipes follow the paper's setting (Section 6: complete linkage on
 protein-structure RMSD matrices, average n about 1968) with synthetic
@@ -16,7 +18,11 @@ available.
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
+import threading
 from dataclasses import dataclass
 
 import numpy as np
@@ -26,10 +32,43 @@ BASE_SEED = 170906816
 LINKAGES = ("single", "complete", "average", "ward")
 
 
-def _torch():
-    import torch  # CPU only: used for multi-threaded fp64 block arithmetic
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_GEN_SRC = os.path.join(_HERE, "_gen.c")
+_GEN_LIB = os.path.join(_HERE, "_gen.so")
+_gen_lock = threading.Lock()
+_gen = None
 
-    return torch
+
+def build(force: bool = False) -> str:
+    """Compile the fixed-order fp64 helper (_gen.c) with gcc."""
+    if force or not os.path.exists(_GEN_LIB) or os.path.getmtime(_GEN_LIB) < os.path.getmtime(_GEN_SRC):
+        tmp = _GEN_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                               "-shared", "-std=gnu11", "-Wall", "-o", tmp, _GEN_SRC, "-lm"])
+        os.replace(tmp, _GEN_LIB)
+    return _GEN_LIB
+
+
+def _lib():
+    global _gen
+    with _gen_lock:
+        if _gen is None:
+            build()
+            lib = ctypes.CDLL(_GEN_LIB)
+            dp, fp, lp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float), \
+                ctypes.POINTER(ctypes.c_int64)
+            lib.synth_euclid.argtypes = [dp, ctypes.c_int64, ctypes.c_int, fp, ctypes.c_double, ctypes.c_int]
+            lib.synth_euclid.restype = ctypes.c_int
+            lib.synth_orthonormal.argtypes = [dp, ctypes.c_int, dp]
+            lib.synth_orthonormal.restype = ctypes.c_int
+            lib.synth_rotate.argtypes = [dp, lp, ctypes.c_int64, ctypes.c_int, dp, dp, dp, dp]
+            lib.synth_rotate.restype = None
+            _gen = lib
+    return _gen
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
 def gaussian_mixture(rng: np.random.Generator, n: int, dim: int, k: int,
@@ -39,8 +78,9 @@ def gaussian_mixture(rng: np.random.Generator, n: int, dim: int, k: int,
 
     Centres ~ U[-box, box]^dim, labels uniform over clusters.  Isotropic
     clusters use one sigma per cluster ~ U[sigma_lo, sigma_hi]; anisotropic
-    clusters use x = c + R diag(s) z with R a random orthogonal matrix (QR of a
-    Gaussian) and s_d ~ U[0.3, 3].
+    clusters use x = c + R diag(s) z with R a random orthogonal matrix (the
+    Q factor, with positive diagonal of R, of a Gaussian matrix, by modified
+    Gram-Schmidt in fixed order) and s_d ~ U[0.3, 3].
     """
     centres = rng.uniform(-box, box, size=(k, dim))
     labels = rng.integers(0, k, size=n)
@@ -48,58 +88,43 @@ def gaussian_mixture(rng: np.random.Generator, n: int, dim: int, k: int,
     if not anisotropic:
         sig = rng.uniform(sigma_lo, sigma_hi, size=k)
         return centres[labels] + z * sig[labels, None]
+    lib = _lib()
     pts = np.empty((n, dim))
+    q = np.empty((dim, dim))
     for c in range(k):
-        q, r = np.linalg.qr(rng.standard_normal((dim, dim)))
-        q = q * np.sign(np.diag(r))[None, :]
-        s = rng.uniform(0.3, 3.0, size=dim)
-        sel = labels == c
-        pts[sel] = centres[c] + (z[sel] * s[None, :]) @ q.T
+        g = np.ascontiguousarray(rng.standard_normal((dim, dim)))
+        if lib.synth_orthonormal(_p(g, ctypes.c_double), dim, _p(q, ctypes.c_double)) != 0:
+            raise ValueError("singular Gaussian matrix")
+        s = np.ascontiguousarray(rng.uniform(0.3, 3.0, size=dim))
+        rows = np.ascontiguousarray(np.nonzero(labels == c)[0].astype(np.int64))
+        cen = np.ascontiguousarray(centres[c])
+        lib.synth_rotate(_p(z, ctypes.c_double), _p(rows, ctypes.c_int64), len(rows), dim,
+                         _p(cen, ctypes.c_double), _p(s, ctypes.c_double), _p(q, ctypes.c_double),
+                         _p(pts, ctypes.c_double))
     return pts
 
 
 def euclidean_matrix(points: np.ndarray, scale_to: float | None = None,
-                     round_decimals: int | None = None, out: np.ndarray | None = None,
-                     block: int = 2048) -> np.ndarray:
+                     round_decimals: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
     """Full n x n fp32 Euclidean distance matrix of float64 points.
 
     Distances are sqrt(max(0, |x|^2 + |y|^2 - 2 x.y)) evaluated in float64
-    block by block, optionally rescaled so the largest distance equals
+    with every sum taken in index order (so the matrix is bit-identical on
+    any host), optionally rescaled so the largest distance equals
     ``scale_to`` and rounded (half to even) to ``round_decimals`` decimals,
-    then rounded once to fp32.  The diagonal is exactly zero.
+    then rounded once to fp32.  The strict upper triangle is computed and
+    mirrored; the diagonal is exactly zero.
     """
-    torch = _torch()
-    x = torch.from_numpy(np.ascontiguousarray(points, dtype=np.float64))
-    n = x.shape[0]
-    sq = (x * x).sum(1)
+    x = np.ascontiguousarray(points, dtype=np.float64)
+    n, dim = x.shape
     if out is None:
         out = np.empty((n, n), dtype=np.float32)
-    out_t = torch.from_numpy(out)
-    buf = torch.empty((min(block, n), n), dtype=torch.float64)
-
-    def fill(r0, r1):
-        b = buf[: r1 - r0]
-        torch.matmul(x[r0:r1], x.T, out=b)
-        b.mul_(-2.0).add_(sq[r0:r1, None]).add_(sq[None, :]).clamp_min_(0.0).sqrt_()
-        return b
-
-    factor = None
-    if scale_to is not None:
-        dmax = 0.0
-        for r0 in range(0, n, block):
-            dmax = max(dmax, float(fill(r0, min(n, r0 + block)).max()))
-        factor = scale_to / dmax if dmax > 0 else 1.0
-    for r0 in range(0, n, block):
-        r1 = min(n, r0 + block)
-        b = fill(r0, r1)
-        if factor is not None:
-            b.mul_(factor)
-        if round_decimals is not None:
-            p = 10.0 ** round_decimals
-            b.mul_(p).round_().div_(p)
-        out_t[r0:r1].copy_(b)
-    idx = np.arange(n)
-    out[idx, idx] = 0.0
+    assert out.shape == (n, n) and out.dtype == np.float32 and out.flags["C_CONTIGUOUS"]
+    rc = _lib().synth_euclid(_p(x, ctypes.c_double), n, dim, _p(out, ctypes.c_float),
+                             float(scale_to) if scale_to is not None else 0.0,
+                             int(round_decimals) if round_decimals is not None else -1)
+    if rc != 0:
+        raise MemoryError("synth_euclid")
     return out
 
 
