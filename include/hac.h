@@ -117,6 +117,40 @@ int hac_run(hac_ctx *ctx, float *dist, int32_t n, int32_t linkage,
             hac_merge *out, uint32_t flags, void *stream);
 
 /*
+ * hac_run_noalloc -- hac_run for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same computation and the same merge list as hac_run on the
+ * same input and options (it runs hac_run's kernels), but the call itself
+ * allocates nothing: a run's device scratch (control block, status word,
+ * first row minima, exchange slots; HAC_NOALLOC_SCRATCH_BYTES bytes) is a
+ * static array of the library, one per device, whose address hac_create
+ * looks up once; the page-locked host word it reads the status back through
+ * is allocated by hac_create too.
+ *   dist:    device pointer, n*n fp32, row-major (caller-owned); used as the
+ *            working matrix and overwritten.  HAC_PRESERVE_INPUT is rejected
+ *            (HAC_EINVAL): a copy would need n*n*4 bytes of workspace.
+ *   n:       1..HAC_NOALLOC_MAX_N; a larger n returns HAC_EINVAL.
+ *   linkage: a hac_linkage value.
+ *   out:     device memory for n-1 records (caller-owned).
+ *   flags:   0 or HAC_MODE_SCAN, optionally with HAC_OUT_DEVICE: then the
+ *            call returns once the work is enqueued and hac_sync() reports the
+ *            status; without it the call waits and returns the run's status.
+ *   stream:  hipStream_t to enqueue on; NULL = HIP's default stream.
+ *   The merge kernel runs on at most HAC_NOALLOC_MAX_WORKGROUPS workgroups
+ *   (HAC_OPT_WORKGROUPS above that is clamped).  hac_get_stats reports the
+ *   run like hac_run's.
+ *   The scratch array is shared by every call on a device and keeps the
+ *   last call's contents (each call clears what must start at zero), so
+ *   calls that overlap on one GPU -- from two contexts, two host threads or
+ *   two streams -- race: the caller serialises them.
+ */
+#define HAC_NOALLOC_MAX_N 65536
+#define HAC_NOALLOC_MAX_WORKGROUPS 64
+#define HAC_NOALLOC_SCRATCH_BYTES 1057280 /* 256 + 256 + 8 * 65536 + 2 * 65 * 4096 */
+int hac_run_noalloc(hac_ctx *ctx, float *dist, int32_t n, int32_t linkage,
+                    hac_merge *out, uint32_t flags, void *stream);
+
+/*
  * hac_batch -- cluster `count` independent instances in one persistent launch.
  *   packed:      device pointer; instance k's n_k x n_k matrix starts at
  *                element offsets[k] (instances must not overlap).

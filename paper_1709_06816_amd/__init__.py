@@ -40,6 +40,9 @@ OPT_AUTOTUNE, OPT_BATCH_BLOCK, OPT_BATCH_GROUP, OPT_GRAPH = 7, 8, 9, 10
 OPT_DEFER = 11
 MAX_N = 65536
 MAX_BATCH_N = 8192
+NOALLOC_MAX_N = 65536
+NOALLOC_MAX_WORKGROUPS = 64
+NOALLOC_SCRATCH_BYTES = 1057280
 
 _STATUS_NAMES = {
     HAC_EINVAL: "HAC_EINVAL", HAC_EINPUT: "HAC_EINPUT", HAC_ENOMEM: "HAC_ENOMEM",
@@ -48,7 +51,7 @@ _STATUS_NAMES = {
 }
 
 # Symbols the library must export (one per declaration in include/hac.h).
-EXPORTS = ("hac_create", "hac_destroy", "hac_run", "hac_batch", "hac_rmsd", "hac_sync", "hac_last_error",
+EXPORTS = ("hac_create", "hac_destroy", "hac_run", "hac_run_noalloc", "hac_batch", "hac_rmsd", "hac_sync", "hac_last_error",
            "hac_set_option", "hac_get_stats", "hac_server_create", "hac_submit", "hac_poll",
            "hac_server_get_stats", "hac_server_last_error", "hac_server_destroy")
 
@@ -104,6 +107,7 @@ def load_library():
         lib.hac_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
         lib.hac_destroy.argtypes = [vp]
         lib.hac_run.argtypes = [vp, vp, i32, i32, vp, u32, vp]
+        lib.hac_run_noalloc.argtypes = [vp, vp, i32, i32, vp, u32, vp]
         lib.hac_batch.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, u32, vp]
         lib.hac_rmsd.argtypes = [vp, vp, i32, i32, vp, u32, vp]
         lib.hac_sync.argtypes = [vp]
@@ -226,6 +230,18 @@ class Context:
                                       ctypes.c_void_p(optr) if optr else None, flags,
                                       ctypes.c_void_p(s) if s else None))
         return res
+
+    def run_noalloc(self, dist_ptr: int, n: int, linkage, out_ptr: int, scan: bool = False, wait: bool = True,
+                    stream=None):
+        """hac_run_noalloc: cluster the n x n fp32 device matrix at
+        ``dist_ptr`` (overwritten) into the n-1 records at device address
+        ``out_ptr``, with the library's static scratch and no allocation.
+        ``wait=False`` returns once enqueued (``sync()`` reports the status)."""
+        flags = (MODE_SCAN if scan else 0) | (0 if wait else OUT_DEVICE)
+        s = _stream_of(stream)
+        self._check(self._lib.hac_run_noalloc(self._h, ctypes.c_void_p(_dev_ptr(dist_ptr)), int(n), _link(linkage),
+                                              ctypes.c_void_p(_dev_ptr(out_ptr)), flags,
+                                              ctypes.c_void_p(s) if s else None))
 
     def rmsd(self, coords, out=None, stream=None):
         """RMSD matrix of n conformations (hac_rmsd): ``coords`` a contiguous

@@ -44,6 +44,7 @@ struct hac_ctx {
 
     void *ws = nullptr;          // control block, statuses, sizes, slots, descriptors
     size_t ws_cap = 0;
+    void *scratch = nullptr;     // this device's static scratch array (hac_run_noalloc)
     float *dcopy = nullptr;      // HAC_PRESERVE_INPUT copy
     size_t dcopy_cap = 0;        // bytes
     void *rmsd_ws = nullptr;     // RMSD producer: coordinate planes, norms, status
@@ -205,9 +206,10 @@ int check_status(hac_ctx *c) {
 
 // Enqueue the read-back of control + status words, then either return
 // (device output) or wait and check.
-int finish(hac_ctx *c, hipStream_t s, int nstatus, hac_merge *out, size_t nrec, uint32_t flags) {
+int finish(hac_ctx *c, hipStream_t s, int nstatus, hac_merge *out, size_t nrec, uint32_t flags,
+           const void *ws) {
     const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
-    HIP_TRY(c, hipMemcpyAsync(c->pinned, c->ws, ctl_bytes + (size_t)nstatus * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->pinned, ws, ctl_bytes + (size_t)nstatus * 4, hipMemcpyDeviceToHost, s));
     c->pending = true;
     c->pending_stream = s;
     c->pending_count = nstatus;
@@ -449,6 +451,18 @@ int hac_create(int device, hac_ctx **out) {
         return HAC_EDEVICE;
     }
     c->lds_max = usable;
+    // The allocation-free entry point's scratch: this device's copy of the
+    // library's static array (the device is current), and the page-locked
+    // word its status comes back through.
+    if (hac::engine_scratch(&c->scratch) != hipSuccess || !c->scratch) {
+        (void)hipGetLastError();
+        hac_destroy(c);
+        return HAC_EDEVICE;
+    }
+    if (ensure_pinned(c, 4096) != HAC_OK) {
+        hac_destroy(c);
+        return HAC_EDEVICE;
+    }
     *out = c;
     return HAC_OK;
 }
@@ -551,15 +565,17 @@ int hac_sync(hac_ctx *c) {
     return check_status(c);
 }
 
-int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags,
-            void *stream) {
-    if (!c) return HAC_EINVAL;
-    c->err.clear();
-    if (!dist) return fail(c, HAC_EINVAL, "dist is NULL");
-    if (n < 1 || n > HAC_MAX_N) return fail(c, HAC_EINVAL, "n=%d outside 1..%d", n, HAC_MAX_N);
-    if (linkage < 0 || linkage > HAC_CENTROID) return fail(c, HAC_EINVAL, "linkage %d is not 0..5", linkage);
-    if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE | HAC_MODE_SCAN)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
-    if (n > 1 && !out) return fail(c, HAC_EINVAL, "out is NULL");
+}  // extern "C"
+
+namespace {
+
+// hac_run and hac_run_noalloc.  noalloc: the device scratch is the static
+// array (c->scratch) instead of the context's workspace, the merge kernel
+// runs on at most HAC_NOALLOC_MAX_WORKGROUPS workgroups, out is device
+// memory, and nothing is allocated (the caller has rejected
+// HAC_PRESERVE_INPUT).
+int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags, void *stream,
+             bool noalloc) {
     int rc = set_device(c);
     if (rc) return rc;
     if (c->pending) {
@@ -587,6 +603,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
         int want = c->opt_wgs > 0 ? (int)c->opt_wgs
                    : (flags & HAC_MODE_SCAN) ? nch
                                              : std::max(2, std::min(64, n / 512));
+        if (noalloc) want = std::min(want, HAC_NOALLOC_MAX_WORKGROUPS);
         g = std::max(1, std::min(want, nch));
         while (g < nch && hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max) ++g;
         const size_t lds = hac::lds_bytes(n, hac::own_rows(n, g), false);
@@ -595,6 +612,8 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
         if (g > cap) g = cap;
         if (hac::lds_bytes(n, hac::own_rows(n, g), false) > c->lds_max)
             return fail(c, HAC_EDEVICE, "n=%d needs more co-resident workgroups than the device holds", n);
+        if (noalloc && g > HAC_NOALLOC_MAX_WORKGROUPS)
+            return fail(c, HAC_EINVAL, "n=%d needs more than %d workgroups", n, HAC_NOALLOC_MAX_WORKGROUPS);
         if (g > 1 && !c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
     } else if (c->opt_defer == 2 && !(flags & HAC_MODE_SCAN)) {
         run_flags |= hac::kFlagDefer;  // one workgroup, deferred rescans on request
@@ -606,10 +625,20 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     const size_t rk_off = st_off + st_bytes, rk_bytes = align_up((size_t)n * 8, kAlign);
     const size_t sl_off = rk_off + rk_bytes;
     const size_t sl_bytes = g > 1 ? (size_t)2 * (g + 1) * hac::kSlotStride * 8 : 0;
-    rc = ensure_dev(c, &c->ws, &c->ws_cap, sl_off + sl_bytes, "workspace");
-    if (rc) return rc;
-    rc = ensure_pinned(c, ctl_bytes + kAlign);
-    if (rc) return rc;
+    char *ws = nullptr;
+    if (noalloc) {
+        // Fits by construction (n <= HAC_NOALLOC_MAX_N, g <= HAC_NOALLOC_MAX_WORKGROUPS);
+        // the pinned staging was allocated by hac_create.
+        if (sl_off + sl_bytes > hac::kNoAllocScratchBytes || ctl_bytes + kAlign > c->pinned_cap)
+            return fail(c, HAC_EINVAL, "n=%d on %d workgroups exceeds the static scratch", n, g);
+        ws = static_cast<char *>(c->scratch);
+    } else {
+        rc = ensure_dev(c, &c->ws, &c->ws_cap, sl_off + sl_bytes, "workspace");
+        if (rc) return rc;
+        rc = ensure_pinned(c, ctl_bytes + kAlign);
+        if (rc) return rc;
+        ws = reinterpret_cast<char *>(c->ws);
+    }
 
     // With HAC_PRESERVE_INPUT the set-up kernel reads the caller's matrix and
     // writes both triangles of the library's working copy (no separate copy).
@@ -621,7 +650,7 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
         D = c->dcopy;
     }
     hac_merge *dev_out = out;
-    if (!(flags & HAC_OUT_DEVICE)) {
+    if (!noalloc && !(flags & HAC_OUT_DEVICE)) {
         size_t cap_bytes = c->dout_cap * sizeof(hac_merge);
         rc = ensure_dev(c, reinterpret_cast<void **>(&c->dout), &cap_bytes, (size_t)(n - 1) * sizeof(hac_merge), "merge buffer");
         if (rc) return rc;
@@ -629,7 +658,6 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
         dev_out = c->dout;
     }
 
-    char *ws = reinterpret_cast<char *>(c->ws);
     hac::Instance inst;
     inst.D = D;
     inst.out = dev_out;
@@ -645,6 +673,9 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     inst.flags = run_flags;
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 
+    // Everything that must start at zero is cleared by fill kernels (no
+    // memset): control block and status, the exchange slots; the set-up
+    // kernel's row minima are filled by launch_run.
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
     if (sl_bytes) HIP_TRY(c, hac::launch_zero(ws + sl_off, sl_bytes / 4, s));
@@ -656,7 +687,41 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
     c->pending_group = g;
     c->pending_graph = 0;
     c->pending_deferred = (run_flags & hac::kFlagDefer) ? 1 : 0;
-    return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags);
+    if (noalloc) return finish(c, s, 1, nullptr, 0, flags, ws);
+    return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags,
+            void *stream) {
+    if (!c) return HAC_EINVAL;
+    c->err.clear();
+    if (!dist) return fail(c, HAC_EINVAL, "dist is NULL");
+    if (n < 1 || n > HAC_MAX_N) return fail(c, HAC_EINVAL, "n=%d outside 1..%d", n, HAC_MAX_N);
+    if (linkage < 0 || linkage > HAC_CENTROID) return fail(c, HAC_EINVAL, "linkage %d is not 0..5", linkage);
+    if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE | HAC_MODE_SCAN)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
+    if (n > 1 && !out) return fail(c, HAC_EINVAL, "out is NULL");
+    return run_impl(c, dist, n, linkage, out, flags, stream, false);
+}
+
+int hac_run_noalloc(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags,
+                    void *stream) {
+    if (!c) return HAC_EINVAL;
+    c->err.clear();
+    if (!dist) return fail(c, HAC_EINVAL, "dist is NULL");
+    if (n < 1 || n > HAC_NOALLOC_MAX_N)
+        return fail(c, HAC_EINVAL, "n=%d outside 1..%d (the static scratch holds the row minima of at most %d items)",
+                    n, HAC_NOALLOC_MAX_N, HAC_NOALLOC_MAX_N);
+    if (linkage < 0 || linkage > HAC_CENTROID) return fail(c, HAC_EINVAL, "linkage %d is not 0..5", linkage);
+    if (flags & HAC_PRESERVE_INPUT)
+        return fail(c, HAC_EINVAL, "HAC_PRESERVE_INPUT needs an n*n workspace; hac_run_noalloc allocates none");
+    if (flags & ~(HAC_OUT_DEVICE | HAC_MODE_SCAN)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
+    if (n > 1 && !out) return fail(c, HAC_EINVAL, "out is NULL");
+    if (!c->scratch) return fail(c, HAC_EDEVICE, "no static scratch on this device");
+    return run_impl(c, dist, n, linkage, out, flags, stream, true);
 }
 
 int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *ns,
@@ -758,7 +823,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->pending_group = B.group;
     c->pending_graph = graphed;
     c->pending_deferred = 0;
-    return finish(c, s, count, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)rec_extent, flags);
+    return finish(c, s, count, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)rec_extent, flags, c->ws);
 }
 
 }  // extern "C"

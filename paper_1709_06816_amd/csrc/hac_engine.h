@@ -156,6 +156,21 @@ struct ServeLaunch {
 hipError_t launch_serve(const ServeLaunch &s, Control *ctl, uint64_t timeout_ticks, hipStream_t stream);
 int serve_occupancy(size_t lds, int block);
 
+// Scratch of the allocation-free entry point (hac_run_noalloc): a static
+// device array holding the control block, the status word, the first row
+// minima (n <= HAC_NOALLOC_MAX_N) and the exchange slots of up to
+// HAC_NOALLOC_MAX_WORKGROUPS workgroups, laid out as hac_run lays out its
+// workspace.
+constexpr size_t kScratchCtlBytes = 256;      // Control, aligned
+constexpr size_t kScratchStatusBytes = 256;   // one status word, aligned
+constexpr size_t kNoAllocScratchBytes = kScratchCtlBytes + kScratchStatusBytes + (size_t)8 * HAC_NOALLOC_MAX_N +
+                                        (size_t)2 * (HAC_NOALLOC_MAX_WORKGROUPS + 1) * kSlotStride * 8;
+static_assert(kNoAllocScratchBytes == HAC_NOALLOC_SCRATCH_BYTES, "hac.h states the scratch size");
+static_assert(sizeof(Control) <= kScratchCtlBytes, "control block fits its scratch slot");
+// Device address of that array on the current device (hipGetSymbolAddress);
+// each device holds its own copy at its own address.
+hipError_t engine_scratch(void **ptr);
+
 // Kernel attribute set-up (dynamic LDS limits); call once per device.
 // `max_lds` is the device's LDS per workgroup; *usable receives the dynamic
 // LDS a launch may request.

@@ -1189,6 +1189,13 @@ __global__ void k_fill_ones(uint32_t *p, size_t words) {
 
 }  // namespace
 
+// The allocation-free entry point's scratch (see engine_scratch).  In host
+// code this name is only a handle for hipGetSymbolAddress: kernels receive
+// the address that call returns, never the name.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+hipError_t engine_scratch(void **ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
 int own_rows(int n, int g) { return ((((n + 63) >> 6) + g - 1) / g) * 64; }
 
 size_t lds_bytes(int n, int own, bool in_kernel_setup) {

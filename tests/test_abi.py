@@ -41,6 +41,7 @@ def test_null_arguments_rejected():
     assert lib.hac_sync(None) == hac.HAC_EINVAL
     assert lib.hac_set_option(None, 1, 1) == hac.HAC_EINVAL
     assert lib.hac_run(None, None, 4, 0, None, 0, None) == hac.HAC_EINVAL
+    assert lib.hac_run_noalloc(None, None, 4, 0, None, 0, None) == hac.HAC_EINVAL
     assert lib.hac_batch(None, None, None, None, None, 0, None, None, 0, None) == hac.HAC_EINVAL
     assert lib.hac_create(0, None) == hac.HAC_EINVAL
     assert lib.hac_get_stats(None, None) == hac.HAC_EINVAL
