@@ -241,6 +241,17 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        groups of two or more workgroups (the default; a
  *                        workgroup alone does better rescanning at once),
  *                        2 = also on one workgroup.
+ *   HAC_OPT_ROUNDS       hac_run, single and complete linkage: merge in rounds
+ *                        instead of one pair per step.  Each round merges every
+ *                        pair of clusters that are each other's nearest
+ *                        neighbour under the key order (D, i, j) (single
+ *                        linkage: the globally closest pair, plus those whose
+ *                        distance is the only minimum of both rows), applies
+ *                        all their updates at once and rescans the rows that
+ *                        need it; the records come out in the order of Section
+ *                        4's loop, byte-identical to it.  0 = never, 1 = for
+ *                        n >= 1024 (the default), 2 = always.  Not used by
+ *                        hac_run_noalloc, HAC_MODE_SCAN or other linkages.
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
@@ -253,7 +264,8 @@ typedef enum {
     HAC_OPT_BATCH_BLOCK = 8,
     HAC_OPT_BATCH_GROUP = 9,
     HAC_OPT_GRAPH = 10,
-    HAC_OPT_DEFER = 11
+    HAC_OPT_DEFER = 11,
+    HAC_OPT_ROUNDS = 12
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 
@@ -280,6 +292,8 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *   forced_rounds:     hac_run with deferred rescans: extra argmin rounds taken
  *                      because a row's lower bound won (see HAC_OPT_DEFER)
  *   deferred:          1 if the last hac_run deferred its rescans
+ *   rounds:            hac_run through rounds of merges (HAC_OPT_ROUNDS): rounds
+ *                      run (0 otherwise)
  */
 typedef struct {
     double kernel_ms;
@@ -295,7 +309,7 @@ typedef struct {
     int32_t graph;
     int64_t forced_rounds;
     int32_t deferred;
-    int32_t reserved;
+    int32_t rounds;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

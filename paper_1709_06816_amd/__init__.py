@@ -38,6 +38,7 @@ MODE_SCAN = 4
 OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE, OPT_PROFILE, OPT_BLOCK = 1, 2, 3, 4, 5, 6
 OPT_AUTOTUNE, OPT_BATCH_BLOCK, OPT_BATCH_GROUP, OPT_GRAPH = 7, 8, 9, 10
 OPT_DEFER = 11
+OPT_ROUNDS = 12
 MAX_N = 65536
 MAX_BATCH_N = 8192
 NOALLOC_MAX_N = 65536
@@ -70,7 +71,7 @@ class _Stats(ctypes.Structure):
                 ("block", ctypes.c_int32), ("phase_avg_ms", ctypes.c_double * 5),
                 ("phase_max_ms", ctypes.c_double * 5), ("group", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("forced_rounds", ctypes.c_int64),
-                ("deferred", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("deferred", ctypes.c_int32), ("rounds", ctypes.c_int32)]
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")
@@ -194,7 +195,7 @@ class Context:
         s = _Stats()
         self._check(self._lib.hac_get_stats(self._h, ctypes.byref(s)))
         out = {f: getattr(s, f) for f, _ in _Stats._fields_
-               if f not in ("reserved", "phase_avg_ms", "phase_max_ms")}
+               if f not in ("phase_avg_ms", "phase_max_ms")}
         out["phase_avg_ms"] = dict(zip(PHASES, list(s.phase_avg_ms)))
         out["phase_max_ms"] = dict(zip(PHASES, list(s.phase_max_ms)))
         return out

@@ -15,6 +15,7 @@
 #include "hac_ctx_info.h"
 #include "hac_engine.h"
 #include "hac_rmsd.h"
+#include "hac_rounds.h"
 
 namespace {
 
@@ -22,6 +23,7 @@ constexpr size_t kAlign = 256;
 constexpr int kDefaultSingleWgN = 1536;
 constexpr int kDeferMinGroup = 2;       // HAC_OPT_DEFER = 1: defer from this many workgroups on
 constexpr int64_t kDefaultTimeoutMs = 10000;
+constexpr int kRoundsMinN = 1024;       // HAC_OPT_ROUNDS = 1: rounds of merges from this n on
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -61,6 +63,7 @@ struct hac_ctx {
     std::unordered_map<std::string, BatchPlan> plans;  // tuned batch plans by size mix
     int64_t opt_graph = 1;
     int64_t opt_defer = 1;
+    int64_t opt_rounds = 1;
     std::unordered_map<std::string, hipGraphExec_t> graphs;  // batch graphs by layout
 
     // State of the last enqueued call, for hac_sync / stats.
@@ -68,6 +71,7 @@ struct hac_ctx {
     hipStream_t pending_stream = nullptr;
     int pending_count = 0;           // status words to check
     int pending_wgs = 0, pending_block = 0, pending_group = 0, pending_graph = 0, pending_deferred = 0;
+    bool pending_rounds = false;
 };
 
 namespace {
@@ -180,6 +184,7 @@ int check_status(hac_ctx *c) {
     c->stats.update_elems = (int64_t)ctl->update_elems;
     c->stats.forced_rounds = (int64_t)ctl->forced;
     c->stats.deferred = c->pending_deferred;
+    c->stats.rounds = c->pending_rounds ? (int32_t)ctl->rounds : 0;
     c->stats.workgroups = c->pending_wgs;
     c->stats.block = c->pending_block;
     c->stats.group = c->pending_group;
@@ -532,6 +537,10 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
         return HAC_OK;
     case HAC_OPT_AUTOTUNE: c->opt_autotune = value != 0; return HAC_OK;
     case HAC_OPT_GRAPH: c->opt_graph = value != 0; return HAC_OK;
+    case HAC_OPT_ROUNDS:
+        if (value > 2) return fail(c, HAC_EINVAL, "rounds mode %lld is not 0, 1 or 2", (long long)value);
+        c->opt_rounds = value;
+        return HAC_OK;
     case HAC_OPT_DEFER:
         if (value > 2) return fail(c, HAC_EINVAL, "defer mode %lld is not 0, 1 or 2", (long long)value);
         c->opt_defer = value;
@@ -569,6 +578,63 @@ int hac_sync(hac_ctx *c) {
 
 namespace {
 
+// hac_run through the round engine (single and complete linkage).
+int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags, hipStream_t s) {
+    if (!c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
+    int G = c->cus * hac::rounds_occupancy();
+    if (c->opt_wgs > 0) G = std::min(G, (int)c->opt_wgs);
+    // Workspace: control | status | first upper row minima (set-up kernel) | round engine.
+    const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
+    const size_t st_off = ctl_bytes, st_bytes = kAlign;
+    const size_t rk_off = st_off + st_bytes, rk_bytes = align_up((size_t)n * 8, kAlign);
+    const size_t ro_off = rk_off + rk_bytes;
+    const hac::RoundsLayout Lo = hac::rounds_layout(n, G);
+    int rc = ensure_dev(c, &c->ws, &c->ws_cap, ro_off + Lo.bytes, "workspace");
+    if (rc) return rc;
+    rc = ensure_pinned(c, ctl_bytes + kAlign);
+    if (rc) return rc;
+    char *ws = reinterpret_cast<char *>(c->ws);
+    float *D = dist;
+    if (flags & HAC_PRESERVE_INPUT) {
+        const size_t bytes = (size_t)n * n * 4;
+        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dcopy), &c->dcopy_cap, bytes, "input copy");
+        if (rc) return rc;
+        D = c->dcopy;
+    }
+    hac_merge *dev_out = out;
+    if (!(flags & HAC_OUT_DEVICE)) {
+        size_t cap_bytes = c->dout_cap * sizeof(hac_merge);
+        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dout), &cap_bytes, (size_t)(n - 1) * sizeof(hac_merge),
+                        "merge buffer");
+        if (rc) return rc;
+        c->dout_cap = cap_bytes / sizeof(hac_merge);
+        dev_out = c->dout;
+    }
+    hac::Instance inst{};
+    inst.D = D;
+    inst.out = dev_out;
+    inst.rowkey = reinterpret_cast<uint64_t *>(ws + rk_off);
+    inst.status = reinterpret_cast<uint32_t *>(ws + st_off);
+    inst.n = n;
+    inst.link = linkage;
+    HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
+    HIP_TRY(c, hac::launch_zero(ws + ro_off + Lo.ctl, sizeof(hac::RoundsCtl) / 4, s));
+    HIP_TRY(c, hac::launch_setup(inst, dist, s));
+    HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    hipError_t e = hac::launch_rounds(D, n, linkage, dev_out, inst.status, reinterpret_cast<hac::Control *>(ws),
+                                      ws + ro_off, G, timeout_ticks(c), s);
+    if (e != hipSuccess) return hip_fail(c, e, "round kernel launch");
+    HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    c->pending_wgs = G;
+    c->pending_block = hac::kRoundsBlock;
+    c->pending_group = G;
+    c->pending_graph = 0;
+    c->pending_deferred = 0;
+    c->pending_rounds = true;
+    return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
+}
+
 // hac_run and hac_run_noalloc.  noalloc: the device scratch is the static
 // array (c->scratch) instead of the context's workspace, the merge kernel
 // runs on at most HAC_NOALLOC_MAX_WORKGROUPS workgroups, out is device
@@ -584,7 +650,11 @@ int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     c->stats = hac_stats{};
+    c->pending_rounds = false;
     if (n == 1) return HAC_OK;
+    if (!noalloc && !(flags & HAC_MODE_SCAN) && (linkage == HAC_SINGLE || linkage == HAC_COMPLETE) &&
+        (c->opt_rounds == 2 || (c->opt_rounds == 1 && n >= kRoundsMinN)))
+        return run_rounds(c, dist, n, linkage, out, flags, s);
 
     // Launch shape: one workgroup for small n, else a co-resident group of
     // a few large workgroups (each merge costs every workgroup one agent-scope
@@ -823,6 +893,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->pending_group = B.group;
     c->pending_graph = graphed;
     c->pending_deferred = 0;
+    c->pending_rounds = false;
     return finish(c, s, count, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)rec_extent, flags, c->ws);
 }
 

@@ -36,7 +36,7 @@ struct Control {
     uint32_t error;            // OR of kErr* over the launch
     uint32_t abort;            // set by a workgroup that gives up: every wait exits
     uint32_t next;             // batch work queue head
-    uint32_t pad0;
+    uint32_t rounds;           // rounds of merges run by the round engine
     unsigned long long rescans;
     unsigned long long rescan_elems;
     unsigned long long update_elems;
@@ -73,6 +73,10 @@ size_t lds_bytes(int n, int own, bool in_kernel_setup);
 
 // Fill `words` u32 with zero on `stream` (a kernel, not a memset node).
 hipError_t launch_zero(void *p, size_t words, hipStream_t stream);
+
+// Set-up kernel alone (validation, -0, mirror, first upper row minima into
+// inst.rowkey, which it fills beforehand); status bits go to inst.status.
+hipError_t launch_setup(const Instance &inst, const float *src, hipStream_t stream);
 
 // Single instance: set-up kernel over the whole device, then the merge kernel
 // on g workgroups (g > 1 uses a cooperative launch so that all are

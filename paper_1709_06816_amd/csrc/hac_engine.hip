@@ -50,6 +50,7 @@
 // round of the deferred mode).
 #include <hip/hip_runtime.h>
 
+#include "hac_dev.h"
 #include "hac_engine.h"
 
 namespace hac {
@@ -68,15 +69,6 @@ constexpr int kMaxWaves = 16;
 // bytes in flight and have only 128 VGPRs per thread.
 template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
 template <int B> constexpr int seg_unroll() { return B >= 1024 ? 4 : 8; }
-
-// Order-preserving map of fp32 onto u32 (zeros are canonical +0 here).
-__device__ __forceinline__ uint32_t ord32(float x) {
-    uint32_t u = __float_as_uint(x);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float unord32(uint32_t o) {
-    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
-}
 
 // Table 1 update, fp32, fixed order, no contraction.  Coefficients are fp64
 // quotients rounded once to fp32 (ai, aj, bij: the per-merge coefficients of
@@ -104,43 +96,6 @@ __device__ __forceinline__ float lw_update(int link, float dki, float dkj, float
     }
     return v == 0.0f ? 0.0f : v;
 }
-
-__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
-
-// Workgroup barrier after which the global stores of every wave of the
-// workgroup are complete (acknowledged by this XCD's L2).
-//
-// Publishing to other workgroups works like this: thread 0 issues an
-// agent-scope release fence and then stores the exchange slot; a reader that
-// sees the slot takes an agent-scope acquire.  On gfx950 the release is
-// "write back this XCD's L2, then wait for my own wave's memory operations",
-// and a plain workgroup barrier waits for no global store at all (each wave
-// counts its own stores, and a workgroup-scope release needs no such wait
-// when all waves share one CU).  So a store issued by another wave just
-// before the barrier can still be in flight when thread 0 writes back the
-// L2 and publishes: it then lands in the L2 as a dirty line after the write
-// back, and a reader on another XCD, whose acquire only invalidates its own
-// caches, fetches the old value from memory.  Entries written in one merge
-// and read by another workgroup in the next (the column half of the update,
-// the mirror of the set-up, a served job's copy-in) were exposed to exactly
-// this, most often in the last merges, where the update is short and the
-// stores are issued right before the barrier.  Making every wave wait for its
-// own stores first closes the window: after this barrier, thread 0's release
-// covers the writes of the whole workgroup.
-__device__ __forceinline__ void barrier_stores_done() {
-    __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) expcnt(0) lgkmcnt(0): this wave's stores are acknowledged
-    __syncthreads();
-}
-
-// Wave-wide reductions from the ROCm device library (DPP lane moves, no LDS
-// round trips); the result is uniform across the wave.  Call with every lane
-// of the wave active.
-extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_min_u64(unsigned long long);
-extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
-
-__device__ __forceinline__ uint64_t wave_min(uint64_t v) { return __ockl_wfred_min_u64(v); }
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) { return __ockl_wfred_add_u64(v); }
 
 // 64-bit value of the lane picked by DPP control CTRL; lanes of rows outside
 // ROW_MASK keep their own value.  All lanes must be active.
@@ -1300,8 +1255,7 @@ hipError_t launch_zero(void *p, size_t words, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_run(const Instance &inst, const float *src, int g, int block, Control *ctl,
-                      uint64_t timeout_ticks, hipStream_t stream, hipEvent_t setup_done) {
+hipError_t launch_setup(const Instance &inst, const float *src, hipStream_t stream) {
     const int T = (inst.n + 63) / 64;
     {
         const size_t words = (size_t)inst.n * 2;  // rowkey: n u64 set to kEmpty
@@ -1312,7 +1266,12 @@ hipError_t launch_run(const Instance &inst, const float *src, int g, int block, 
     }
     hipLaunchKernelGGL(k_setup, dim3((T + kSetupStrip - 1) / kSetupStrip, T), dim3(kSetupBlock), 0, stream, inst,
                        src);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_run(const Instance &inst, const float *src, int g, int block, Control *ctl,
+                      uint64_t timeout_ticks, hipStream_t stream, hipEvent_t setup_done) {
+    hipError_t e = launch_setup(inst, src, stream);
     if (e != hipSuccess) return e;
     if (setup_done) {
         e = hipEventRecord(setup_done, stream);

@@ -1,0 +1,45 @@
+// Internal interface of the round engine (hac_rounds.hip): single and
+// complete linkage by rounds of merges of reciprocal nearest neighbours.
+// Not installed; the public interface is hac.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hac_engine.h"
+
+namespace hac {
+
+constexpr int kRoundsBlock = 1024;     // threads per workgroup of the round kernel
+constexpr int kRoundsMaxPairs = 1024;  // pairs merged in one round at most
+
+// Control block of a round-engine launch (device memory, zeroed before it).
+struct RoundsCtl {
+    uint32_t bar;             // grid barrier arrivals (monotonic)
+    uint32_t abort;           // set by a workgroup that gives up
+    uint32_t pairs;           // pairs claimed in the current round
+    uint32_t resc;            // rows queued for a rescan in the current round
+    uint32_t pad[4];
+};
+
+// Device workspace of one round-engine run on an n-item instance with G
+// workgroups; offsets in bytes from the workspace base (256-byte aligned).
+struct RoundsLayout {
+    size_t ctl, rk, cnt, size, role, resc, pairs, k1, rec, key, bytes;
+};
+RoundsLayout rounds_layout(int n, int G);
+
+// Workgroups of the round kernel that fit on one CU.
+int rounds_occupancy();
+
+// Merge kernel of the round engine on G co-resident workgroups (cooperative
+// launch), then the kernel that writes the records in merge order to `out`.
+// The matrix `D` must be the symmetric working matrix written by the set-up
+// kernel (its status word `status` is read first: on kErrInput nothing runs).
+// `ws` is the workspace laid out by rounds_layout (its control block zeroed
+// beforehand).  link is HAC_SINGLE or HAC_COMPLETE.
+// Errors and statistics go to `ctl` (rescans, rescan_elems, update_elems,
+// rounds).
+hipError_t launch_rounds(float *D, int n, int link, hac_merge *out, const uint32_t *status, Control *ctl, void *ws,
+                         int G, uint64_t timeout_ticks, hipStream_t stream);
+
+}  // namespace hac

@@ -1,0 +1,507 @@
+// Round engine: single and complete linkage by rounds of merges.
+//
+// The merge list is the one of Section 4 (steps 1-4): n-1 times, merge the
+// pair of live clusters with the lexicographically smallest key
+// (D, i, j), i < j, keep slot i.  For single and complete linkage the
+// Lance-Williams update is min / max (Table 1), exact in fp32 and independent
+// of the order in which merges are applied, and Section 2.1's remark that
+// single linkage is Prim's minimum spanning tree in disguise points the way:
+// many merges of such a hierarchy are independent of each other and can be
+// made at once.  Which ones, exactly:
+//
+//  * Complete linkage.  With the survivor keeping the smaller slot, the key
+//    order is reducible: after merging i and j, key(i+j, k) >=
+//    min(key(i, k), key(j, k)) holds exactly (the max keeps or raises the
+//    value, and the pair's index part (min(i,k), max(i,k)) is that of
+//    key(i, k)).  So every reciprocal-nearest-neighbour pair under the key
+//    order (a's smallest key is with b and b's with a) is a merge of the
+//    sequential run, with the same record, and all of them can be merged
+//    in one round.  The sequential run's keys then strictly increase, so
+//    sorting all records by (h, i, round) gives its order.
+//  * Single linkage.  min can lower a key's index part (a tie at the same
+//    value moves from column j to the smaller i), so reducibility in key
+//    order fails under ties.  A round merges the global smallest key (the
+//    sequential run's next merge) and every reciprocal pair whose value is
+//    the only minimum of both rows (strict): such a pair is isolated at its
+//    height now and later, so it is a merge of the sequential run with the
+//    same record; within one height and survivor, merges appear in the run
+//    in round order.  Sorting by (h, i, round) again gives the order.
+//
+// Per round, three phases separated by grid barriers (every workgroup is
+// co-resident; cooperative launch):
+//   A  detect: each workgroup reads the cached full-row minimum of its rows
+//      (rk: ord(value):32 | partner:16, ties to the smallest partner) and
+//      claims the reciprocal (and, for single, strict) pairs, writes their
+//      merge records, and publishes its rows' smallest pair key.
+//   B  update: every workgroup loads the round's pairs (plus the global
+//      smallest key if it was not claimed) and takes (64 columns x 64 pairs)
+//      units: v = min/max(D[i][c], D[j][c]) written to both D[i][c] and
+//      D[c][i].  Entries between two clusters merged in the same round get
+//      contributions from four lanes (columns i_q and j_q of pair p and
+//      vice versa) combined with atomic min/max, which is idempotent, so the
+//      result is the same whatever the interleaving.  Rows whose cached
+//      partner merged: complete -> queued for a rescan; single -> the
+//      partner moves to i (the value cannot change) and the count of
+//      entries equal to the minimum drops when both merged entries had it.
+//   C  refresh: retire the j's, rescan the survivors' rows and the queued
+//      rows (full rows, counting the entries equal to the minimum).
+// A last kernel writes the records in merge order (rank of each record's
+// key among all keys).
+#include <hip/hip_runtime.h>
+
+#include "hac_dev.h"
+#include "hac_rounds.h"
+
+namespace hac {
+namespace {
+
+constexpr uint64_t kNone = ~0ull;
+constexpr int B = kRoundsBlock;
+constexpr int W = B / 64;
+constexpr int kPairsPerUnit = 64;   // pairs one wave applies to its 64 columns
+constexpr int kUnroll = 4;          // pairs in flight per lane
+constexpr int kMaskWords = (HAC_MAX_N + 31) / 32;
+
+__device__ __forceinline__ int partner_of(uint64_t e) { return (int)((e >> 16) & 0xFFFFull); }
+__device__ __forceinline__ uint32_t value_of(uint64_t e) { return (uint32_t)(e >> 32); }
+
+__device__ __forceinline__ float lw_minmax(int link, float a, float b) {
+    return link == HAC_SINGLE ? fminf(a, b) : fmaxf(a, b);
+}
+
+// *p = min/max(*p, v) (single / complete), agent scope.
+__device__ void atomic_minmax(float *p, float v, int link) {
+    uint32_t *q = reinterpret_cast<uint32_t *>(p);
+    uint32_t cur = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const float c = __uint_as_float(cur);
+        const float nv = lw_minmax(link, c, v);
+        if (__float_as_uint(nv) == cur) return;
+        if (__hip_atomic_compare_exchange_strong(q, &cur, __float_as_uint(nv), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+    }
+}
+
+__shared__ uint32_t s_live[kMaskWords];          // live bitmask of all slots (same on every workgroup)
+__shared__ int2 s_pair[kRoundsMaxPairs + 1];     // this round's pairs (i, j)
+__shared__ uint64_t s_red[W];
+__shared__ int s_np, s_p0;
+__shared__ uint32_t s_fail;
+
+__device__ __forceinline__ bool live_at(int c) { return (s_live[c >> 5] >> (c & 31)) & 1u; }
+
+// Grid barrier: every workgroup's writes before it are visible to every
+// workgroup after it (stores complete, then an agent-scope release and
+// acquire around a monotonic arrival counter).  Returns false, the same for
+// every thread of the workgroup, if the launch was aborted or the wait
+// exceeded the watchdog (which then aborts it for all).
+__device__ bool grid_sync(RoundsCtl *rc, Control *ctl, uint32_t &gen, uint32_t G, uint64_t timeout) {
+    barrier_stores_done();
+    if (threadIdx.x == 0) {
+        ++gen;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&rc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = gen * G;
+        uint32_t fail = 0;
+        const uint64_t t0 = wall_clock64();
+        for (uint32_t it = 1;; ++it) {
+            if (__hip_atomic_load(&rc->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if ((it & 63u) == 0) {
+                if (__hip_atomic_load(&rc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    fail = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > timeout) {
+                    atomicOr(&ctl->error, kErrTimeout);
+                    __hip_atomic_store(&rc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    fail = 1;
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_fail = fail;
+    }
+    __syncthreads();
+    return s_fail == 0;
+}
+
+template <class T>
+__device__ T block_min(T v) {
+    v = wave_min(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) s_red[wv] = v;
+    __syncthreads();
+    T r = s_red[0];
+#pragma unroll
+    for (int q = 1; q < W; ++q) r = r < s_red[q] ? r : s_red[q];
+    return r;
+}
+
+// One wave recomputes row r's cache entry over the live columns other than
+// r: rk[r] = ord(min):32 | smallest column attaining it:16, cnt[r] = number
+// of live columns attaining it (kNone / 0 if no live column is left).
+__device__ void rescan_row(const float *__restrict__ D, int n, int r, uint64_t *rk, int32_t *cnt,
+                           unsigned long long &elems) {
+    const int lane = threadIdx.x & 63;
+    const float *row = D + (size_t)r * n;
+    uint32_t mv = 0xFFFFFFFFu;
+    int mc = 0, mn = 0;
+    auto take = [&](float x, int col) {
+        const uint32_t o = ord32(x);
+        if (o < mv) {
+            mv = o;
+            mc = col;
+            mn = 1;
+        } else if (o == mv) {
+            ++mn;  // columns arrive in increasing order per lane: mc stays the smallest
+        }
+        ++elems;
+    };
+    if ((n & 3) == 0) {
+        constexpr int U = 8;
+        const int nq = n >> 2;
+        for (int q0 = 0; q0 < nq; q0 += 64 * U) {
+            float4 x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * 64 + lane;
+                x[u] = q < nq ? *reinterpret_cast<const float4 *>(row + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * 64 + lane;
+                if (q >= nq) continue;
+                uint32_t m = (s_live[q >> 3] >> ((q & 7) * 4)) & 0xFu;
+                if ((r >> 2) == q) m &= ~(1u << (r & 3));
+                if (!m) continue;
+                if (m & 1u) take(x[u].x, 4 * q);
+                if (m & 2u) take(x[u].y, 4 * q + 1);
+                if (m & 4u) take(x[u].z, 4 * q + 2);
+                if (m & 8u) take(x[u].w, 4 * q + 3);
+            }
+        }
+    } else {
+        constexpr int U = 8;
+        for (int c0 = 0; c0 < n; c0 += 64 * U) {
+            float x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + u * 64 + lane;
+                x[u] = c < n ? row[c] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + u * 64 + lane;
+                if (c < n && c != r && live_at(c)) take(x[u], c);
+            }
+        }
+    }
+    const uint64_t mine = mn ? (((uint64_t)mv << 32) | ((uint64_t)mc << 16)) : kNone;
+    const uint64_t best = wave_min(mine);
+    const unsigned long long ties = wave_sum((mn && mv == value_of(best)) ? (unsigned long long)mn : 0ull);
+    if (lane == 0) {
+        rk[r] = best;
+        cnt[r] = (int32_t)ties;
+    }
+}
+
+struct Views {
+    RoundsCtl *rc;
+    uint64_t *rk;      // n row entries
+    int32_t *cnt;      // n counts of entries equal to the row minimum
+    int32_t *size;     // n cluster sizes
+    int32_t *role;     // n: +(p+1) survivor of pair p this round, -(p+1) retired, 0 otherwise
+    int32_t *resc;     // rows queued for a rescan this round
+    int2 *pairs;       // kRoundsMaxPairs claimed pairs
+    uint64_t *k1;      // G smallest pair keys (one per workgroup)
+    int4 *rec;         // n-1 records in claim order
+    uint64_t *key;     // their sort keys ord(h):32 | i:16 | round:16
+};
+
+__device__ Views views(char *ws, const RoundsLayout &Lo) {
+    Views v;
+    v.rc = reinterpret_cast<RoundsCtl *>(ws + Lo.ctl);
+    v.rk = reinterpret_cast<uint64_t *>(ws + Lo.rk);
+    v.cnt = reinterpret_cast<int32_t *>(ws + Lo.cnt);
+    v.size = reinterpret_cast<int32_t *>(ws + Lo.size);
+    v.role = reinterpret_cast<int32_t *>(ws + Lo.role);
+    v.resc = reinterpret_cast<int32_t *>(ws + Lo.resc);
+    v.pairs = reinterpret_cast<int2 *>(ws + Lo.pairs);
+    v.k1 = reinterpret_cast<uint64_t *>(ws + Lo.k1);
+    v.rec = reinterpret_cast<int4 *>(ws + Lo.rec);
+    v.key = reinterpret_cast<uint64_t *>(ws + Lo.key);
+    return v;
+}
+
+__global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int link, const uint32_t *status,
+                                                         Control *ctl, char *ws, RoundsLayout Lo, uint64_t timeout) {
+    const Views V = views(ws, Lo);
+    const uint32_t G = gridDim.x;
+    const int w = (int)blockIdx.x, tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int gw = w * W + wv, NW = (int)G * W;
+    unsigned long long st_upd = 0, st_resc = 0, st_rows = 0;
+    // The set-up kernel has finished: its verdict is final.
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
+
+    const int words = (n + 31) >> 5;
+    for (int q = tid; q < words; q += B) {
+        const int rem = n - q * 32;
+        s_live[q] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+    }
+    for (int k = w * B + tid; k < n; k += (int)G * B) {
+        V.size[k] = 1;
+        V.role[k] = 0;
+    }
+    __syncthreads();
+    // First cache entries: every row's minimum over the whole row.
+    for (int r = gw; r < n; r += NW) {
+        rescan_row(D, n, r, V.rk, V.cnt, st_resc);
+        ++st_rows;
+    }
+    uint32_t gen = 0;
+    if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+
+    const int R = (n + (int)G - 1) / (int)G;  // rows per workgroup in phase A
+    const int r0 = w * R, r1 = min(n, r0 + R);
+    const int nblocks = (n + 63) >> 6;
+    int merges = 0, round = 0;
+    while (merges < n - 1) {
+        // ---- A: claim reciprocal (single: and strict) pairs -------------
+        if (w == 0 && tid == 0) V.rc->resc = 0;
+        uint64_t kmin = kNone;
+        for (int a = r0 + tid; a < r1; a += B) {
+            if (!live_at(a)) continue;
+            const uint64_t e = V.rk[a];
+            if (e == kNone) continue;
+            const int b = partner_of(e);
+            const uint32_t v = value_of(e);
+            kmin = umin64(kmin, ((uint64_t)v << 32) | ((uint64_t)min(a, b) << 16) | (uint64_t)max(a, b));
+            if (a > b) continue;
+            const uint64_t eb = V.rk[b];
+            if (partner_of(eb) != a) continue;
+            if (link == HAC_SINGLE && (V.cnt[a] != 1 || V.cnt[b] != 1)) continue;
+            const uint32_t slot = atomicAdd(&V.rc->pairs, 1u);
+            if (slot >= (uint32_t)kRoundsMaxPairs) continue;
+            V.pairs[slot] = make_int2(a, b);
+            V.role[a] = (int)slot + 1;
+            V.role[b] = -((int)slot + 1);
+            V.rec[merges + slot] = make_int4(a, b, __float_as_int(unord32(v)), V.size[a] + V.size[b]);
+            V.key[merges + slot] = ((uint64_t)v << 32) | ((uint64_t)a << 16) | (uint64_t)round;
+        }
+        kmin = block_min(kmin);
+        if (tid == 0) V.k1[w] = kmin;
+        if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+
+        // ---- B: Lance-Williams updates of every pair --------------------
+        {
+            uint64_t k1 = kNone;
+            for (int t = tid; t < (int)G; t += B) k1 = umin64(k1, V.k1[t]);
+            k1 = block_min(k1);
+            const uint32_t claimed = __hip_atomic_load(&V.rc->pairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int p0 = (int)min(claimed, (uint32_t)kRoundsMaxPairs);
+            for (int t = tid; t < p0; t += B) s_pair[t] = V.pairs[t];
+            if (tid == 0) {
+                int np = p0;
+                if (k1 == kNone) {
+                    atomicOr(&ctl->error, kErrInternal);
+                    __hip_atomic_store(&V.rc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    np = -1;
+                } else {
+                    const int ka = (int)((k1 >> 16) & 0xFFFFull), kb = (int)(k1 & 0xFFFFull);
+                    // The smallest key is a reciprocal pair; if no slot holds
+                    // it (single: not strict; or beyond the round's cap) it is
+                    // merged as an extra pair, the same on every workgroup.
+                    if (V.role[ka] <= 0) {
+                        s_pair[p0] = make_int2(ka, kb);
+                        np = p0 + 1;
+                        if (w == 0)
+                            V.rec[merges + p0] = make_int4(ka, kb, __float_as_int(unord32((uint32_t)(k1 >> 32))),
+                                                           V.size[ka] + V.size[kb]);
+                        if (w == 0)
+                            V.key[merges + p0] = (k1 & 0xFFFFFFFF00000000ull) | ((uint64_t)ka << 16) | (uint64_t)round;
+                    }
+                }
+                s_np = np;
+                s_p0 = p0;
+            }
+            __syncthreads();
+            const int np = s_np;
+            if (np < 0) return;
+            const int extra_i = np > p0 ? s_pair[p0].x : -1, extra_j = np > p0 ? s_pair[p0].y : -1;
+            const int npr = (np + kPairsPerUnit - 1) / kPairsPerUnit;
+            const int units = nblocks * npr;
+            for (int u = gw; u < units; u += NW) {
+                const int cb = u % nblocks, pr = u / nblocks;
+                const int c = cb * 64 + lane;
+                const bool lv = c < n && live_at(c);
+                if (__ballot(lv) == 0ull) continue;
+                int rl = lv ? V.role[c] : 0;
+                if (c == extra_i) rl = p0 + 1;
+                if (c == extra_j) rl = -(p0 + 1);
+                const int q = rl > 0 ? rl - 1 : -rl - 1;  // this column's own pair (rl != 0)
+                const uint64_t ec = (lv && rl == 0) ? V.rk[c] : kNone;
+                const uint32_t valc = value_of(ec);
+                const int pic = partner_of(ec);
+                const int pb = pr * kPairsPerUnit, pe = min(np, pb + kPairsPerUnit);
+                for (int p = pb; p < pe; p += kUnroll) {
+                    float a[kUnroll], b[kUnroll];
+#pragma unroll
+                    for (int t = 0; t < kUnroll; ++t) {
+                        const int pp = p + t;
+                        const bool use = lv && pp < pe && !(rl != 0 && q == pp);
+                        const int2 ij = s_pair[pp < pe ? pp : pb];
+                        a[t] = use ? D[(size_t)ij.x * n + c] : 0.0f;
+                        b[t] = use ? D[(size_t)ij.y * n + c] : 0.0f;
+                    }
+#pragma unroll
+                    for (int t = 0; t < kUnroll; ++t) {
+                        const int pp = p + t;
+                        if (!lv || pp >= pe || (rl != 0 && q == pp)) continue;
+                        const int2 ij = s_pair[pp];
+                        float v = lw_minmax(link, a[t], b[t]);
+                        if (v == 0.0f) v = 0.0f;
+                        if (rl == 0) {
+                            D[(size_t)ij.x * n + c] = v;
+                            D[(size_t)c * n + ij.x] = v;
+                            ++st_upd;
+                            if (link == HAC_COMPLETE) {
+                                if (pic == ij.x || pic == ij.y) V.resc[atomicAdd(&V.rc->resc, 1u)] = c;
+                            } else {
+                                if (ord32(v) == valc)
+                                    atomicMin(reinterpret_cast<unsigned long long *>(V.rk + c),
+                                              (unsigned long long)(((uint64_t)valc << 32) | ((uint64_t)ij.x << 16)));
+                                if (ord32(a[t]) == valc && ord32(b[t]) == valc) atomicSub(V.cnt + c, 1);
+                            }
+                        } else {
+                            // Column c is i_q or j_q of another pair q: its part of
+                            // the entry between the two merged clusters.
+                            const int iq = s_pair[q].x;
+                            atomic_minmax(D + (size_t)ij.x * n + iq, v, link);
+                            atomic_minmax(D + (size_t)iq * n + ij.x, v, link);
+                        }
+                    }
+                }
+            }
+        }
+        if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+
+        // ---- C: retire, rescan survivors and rows whose partner merged --
+        {
+            const int np = s_np;
+            for (int t = tid; t < np; t += B) {
+                const int j = s_pair[t].y;
+                atomicAnd(&s_live[j >> 5], ~(1u << (j & 31)));
+            }
+            if (w == 0) {
+                for (int t = tid; t < np; t += B) {
+                    const int2 ij = s_pair[t];
+                    V.size[ij.x] += V.size[ij.y];
+                    V.rk[ij.y] = kNone;
+                    V.role[ij.x] = 0;
+                    V.role[ij.y] = 0;
+                }
+                if (tid == 0) V.rc->pairs = 0;
+            }
+            __syncthreads();
+            const int nr = link == HAC_COMPLETE
+                               ? (int)__hip_atomic_load(&V.rc->resc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : 0;
+            for (int t = gw; t < np + nr; t += NW) {
+                const int r = t < np ? s_pair[t].x : V.resc[t - np];
+                rescan_row(D, n, r, V.rk, V.cnt, st_resc);
+                ++st_rows;
+            }
+            merges += np;
+            ++round;
+        }
+        if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+    }
+    // Statistics (rows rescanned counts waves, so only lane 0's count).
+    const unsigned long long rows = wave_sum(lane == 0 ? st_rows : 0ull);
+    const unsigned long long re = wave_sum(st_resc);
+    const unsigned long long up = wave_sum(st_upd);
+    if (lane == 0) {
+        atomicAdd(&ctl->rescans, rows);
+        atomicAdd(&ctl->rescan_elems, re);
+        atomicAdd(&ctl->update_elems, up);
+    }
+    if (w == 0 && tid == 0) ctl->rounds = (uint32_t)round;
+}
+
+// Records in merge order: record r goes to the rank of its key among all
+// m keys (keys are distinct: one survivor merges once per round).
+__global__ __launch_bounds__(256) void k_rank(const int4 *__restrict__ rec, const uint64_t *__restrict__ key, int m,
+                                              hac_merge *out, const uint32_t *status) {
+    constexpr int kTileKeys = 2048;
+    __shared__ uint64_t tile[kTileKeys];
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
+    const int r = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    const uint64_t mine = r < m ? key[r] : kNone;
+    int rank = 0;
+    for (int t0 = 0; t0 < m; t0 += kTileKeys) {
+        const int cnt = min(kTileKeys, m - t0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) tile[t] = key[t0 + t];
+        __syncthreads();
+        for (int t = 0; t < cnt; ++t) rank += tile[t] < mine;
+    }
+    if (r < m) reinterpret_cast<int4 *>(out)[rank] = rec[r];
+}
+
+}  // namespace
+
+RoundsLayout rounds_layout(int n, int G) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    RoundsLayout L{};
+    size_t off = 0;
+    L.ctl = off;   off += al(sizeof(RoundsCtl));
+    L.rk = off;    off += al((size_t)n * 8);
+    L.cnt = off;   off += al((size_t)n * 4);
+    L.size = off;  off += al((size_t)n * 4);
+    L.role = off;  off += al((size_t)n * 4);
+    L.resc = off;  off += al((size_t)n * 4);
+    L.pairs = off; off += al((size_t)kRoundsMaxPairs * 8);
+    L.k1 = off;    off += al((size_t)G * 8);
+    L.rec = off;   off += al((size_t)(n > 1 ? n - 1 : 1) * 16);
+    L.key = off;   off += al((size_t)(n > 1 ? n - 1 : 1) * 8);
+    L.bytes = off;
+    return L;
+}
+
+int rounds_occupancy() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(&k_rounds), kRoundsBlock,
+                                                     0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return blocks < 1 ? 1 : blocks;
+}
+
+hipError_t launch_rounds(float *D, int n, int link, hac_merge *out, const uint32_t *status, Control *ctl, void *ws,
+                         int G, uint64_t timeout_ticks, hipStream_t stream) {
+    const RoundsLayout Lo = rounds_layout(n, G);
+    float *a0 = D;
+    int a1 = n;
+    int a2 = link;
+    const uint32_t *a3 = status;
+    Control *a4 = ctl;
+    char *a5 = static_cast<char *>(ws);
+    RoundsLayout a6 = Lo;
+    uint64_t a7 = timeout_ticks;
+    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_rounds), dim3(G), dim3(kRoundsBlock),
+                                              args, 0, stream);
+    if (e != hipSuccess) return e;
+    const int m = n - 1;
+    hipLaunchKernelGGL(k_rank, dim3((m + 255) / 256), dim3(256), 0, stream,
+                       reinterpret_cast<const int4 *>(static_cast<char *>(ws) + Lo.rec),
+                       reinterpret_cast<const uint64_t *>(static_cast<char *>(ws) + Lo.key), m, out, status);
+    return hipGetLastError();
+}
+
+}  // namespace hac

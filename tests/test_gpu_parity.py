@@ -39,8 +39,12 @@ def torch():
 
 @pytest.fixture(scope="module")
 def ctx(torch):
+    # This file covers the one-merge-per-step engine (every linkage, batch,
+    # serving); single and complete linkage merged in rounds are covered by
+    # test_gpu_rounds.py and test_gpu_digests.py.
     import paper_1709_06816_amd as hac
     c = hac.Context(0)
+    c.set_option(hac.OPT_ROUNDS, 0)
     yield c
     c.close()
 
