@@ -480,6 +480,7 @@ def main():
             "rescans": stats["rescans"], "rescan_elems": stats["rescan_elems"],
             "update_elems": stats["update_elems"],
             "deferred_rescans": bool(stats["deferred"]), "forced_rounds": stats["forced_rounds"],
+            "merge_rounds": stats["rounds"],
             "traffic_gbs": None if traffic is None else traffic / (kernel_ms / 1000.0) / 1e9,
             "note": "latency-bound: one grid-wide exchange per merge; rescans run during the exchange wait",
             "setup_kernel": {"kernel": "k_setup", "ms": init_ms, "alg_bytes": alg_bytes_setup(n),

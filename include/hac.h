@@ -250,8 +250,13 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        all their updates at once and rescans the rows that
  *                        need it; the records come out in the order of Section
  *                        4's loop, byte-identical to it.  0 = never, 1 = for
- *                        n >= 1024 (the default), 2 = always.  Not used by
- *                        hac_run_noalloc, HAC_MODE_SCAN or other linkages.
+ *                        n >= 1024 (the default; the remaining merges go to the
+ *                        one-merge-per-step kernel once rounds merge few pairs
+ *                        each: near the end of a run, and early for single
+ *                        linkage on input with many equal values), 2 = always,
+ *                        rounds to the end.  Not
+ *                        used by hac_run_noalloc, HAC_MODE_SCAN or other
+ *                        linkages.
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
@@ -294,6 +299,10 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *   deferred:          1 if the last hac_run deferred its rescans
  *   rounds:            hac_run through rounds of merges (HAC_OPT_ROUNDS): rounds
  *                      run (0 otherwise)
+ *   handed_over:       1 if those rounds stopped part-way (few merges per round:
+ *                      the last ones of a run, or single linkage on input with
+ *                      many equal values) and the one-merge-per-step kernel made
+ *                      the remaining merges
  */
 typedef struct {
     double kernel_ms;
@@ -310,6 +319,8 @@ typedef struct {
     int64_t forced_rounds;
     int32_t deferred;
     int32_t rounds;
+    int32_t handed_over;
+    int32_t reserved;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

@@ -72,6 +72,7 @@ struct hac_ctx {
     int pending_count = 0;           // status words to check
     int pending_wgs = 0, pending_block = 0, pending_group = 0, pending_graph = 0, pending_deferred = 0;
     bool pending_rounds = false;
+    int pending_seq_wgs = 0, pending_seq_block = 0, pending_seq_deferred = 0;  // kernel queued behind the rounds
 };
 
 namespace {
@@ -189,6 +190,12 @@ int check_status(hac_ctx *c) {
     c->stats.block = c->pending_block;
     c->stats.group = c->pending_group;
     c->stats.graph = c->pending_graph;
+    if (c->pending_rounds && c->pending_count == 1 && (st[0] & hac::kHandover)) {
+        // The round engine handed the rest of the merges to the kernel
+        // queued behind it.
+        c->stats.handed_over = 1;
+        c->stats.deferred = c->pending_seq_deferred;
+    }
     const double khz = c->wallclock_khz > 0 ? c->wallclock_khz : 100000.0;
     for (int p = 0; p < 5; ++p) {
         c->stats.phase_avg_ms[p] = (double)ctl->prof_sum[p] / khz / std::max(1, c->pending_wgs);
@@ -578,84 +585,9 @@ int hac_sync(hac_ctx *c) {
 
 namespace {
 
-// hac_run through the round engine (single and complete linkage).
-int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags, hipStream_t s) {
-    if (!c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
-    int G = c->cus * hac::rounds_occupancy();
-    if (c->opt_wgs > 0) G = std::min(G, (int)c->opt_wgs);
-    // Workspace: control | status | first upper row minima (set-up kernel) | round engine.
-    const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
-    const size_t st_off = ctl_bytes, st_bytes = kAlign;
-    const size_t rk_off = st_off + st_bytes, rk_bytes = align_up((size_t)n * 8, kAlign);
-    const size_t ro_off = rk_off + rk_bytes;
-    const hac::RoundsLayout Lo = hac::rounds_layout(n, G);
-    int rc = ensure_dev(c, &c->ws, &c->ws_cap, ro_off + Lo.bytes, "workspace");
-    if (rc) return rc;
-    rc = ensure_pinned(c, ctl_bytes + kAlign);
-    if (rc) return rc;
-    char *ws = reinterpret_cast<char *>(c->ws);
-    float *D = dist;
-    if (flags & HAC_PRESERVE_INPUT) {
-        const size_t bytes = (size_t)n * n * 4;
-        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dcopy), &c->dcopy_cap, bytes, "input copy");
-        if (rc) return rc;
-        D = c->dcopy;
-    }
-    hac_merge *dev_out = out;
-    if (!(flags & HAC_OUT_DEVICE)) {
-        size_t cap_bytes = c->dout_cap * sizeof(hac_merge);
-        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dout), &cap_bytes, (size_t)(n - 1) * sizeof(hac_merge),
-                        "merge buffer");
-        if (rc) return rc;
-        c->dout_cap = cap_bytes / sizeof(hac_merge);
-        dev_out = c->dout;
-    }
-    hac::Instance inst{};
-    inst.D = D;
-    inst.out = dev_out;
-    inst.rowkey = reinterpret_cast<uint64_t *>(ws + rk_off);
-    inst.status = reinterpret_cast<uint32_t *>(ws + st_off);
-    inst.n = n;
-    inst.link = linkage;
-    HIP_TRY(c, hipEventRecord(c->ev[0], s));
-    HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
-    HIP_TRY(c, hac::launch_zero(ws + ro_off + Lo.ctl, sizeof(hac::RoundsCtl) / 4, s));
-    HIP_TRY(c, hac::launch_setup(inst, dist, s));
-    HIP_TRY(c, hipEventRecord(c->ev[1], s));
-    hipError_t e = hac::launch_rounds(D, n, linkage, dev_out, inst.status, reinterpret_cast<hac::Control *>(ws),
-                                      ws + ro_off, G, timeout_ticks(c), s);
-    if (e != hipSuccess) return hip_fail(c, e, "round kernel launch");
-    HIP_TRY(c, hipEventRecord(c->ev[2], s));
-    c->pending_wgs = G;
-    c->pending_block = hac::kRoundsBlock;
-    c->pending_group = G;
-    c->pending_graph = 0;
-    c->pending_deferred = 0;
-    c->pending_rounds = true;
-    return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
-}
-
-// hac_run and hac_run_noalloc.  noalloc: the device scratch is the static
-// array (c->scratch) instead of the context's workspace, the merge kernel
-// runs on at most HAC_NOALLOC_MAX_WORKGROUPS workgroups, out is device
-// memory, and nothing is allocated (the caller has rejected
-// HAC_PRESERVE_INPUT).
-int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags, void *stream,
-             bool noalloc) {
-    int rc = set_device(c);
-    if (rc) return rc;
-    if (c->pending) {
-        rc = hac_sync(c);
-        (void)rc;
-    }
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    c->stats = hac_stats{};
-    c->pending_rounds = false;
-    if (n == 1) return HAC_OK;
-    if (!noalloc && !(flags & HAC_MODE_SCAN) && (linkage == HAC_SINGLE || linkage == HAC_COMPLETE) &&
-        (c->opt_rounds == 2 || (c->opt_rounds == 1 && n >= kRoundsMinN)))
-        return run_rounds(c, dist, n, linkage, out, flags, s);
-
+// Launch plan of the one-merge-per-step kernel for hac_run: workgroups g,
+// threads per workgroup and kFlag* bits.
+int plan_seq(hac_ctx *c, int32_t n, uint32_t flags, bool noalloc, int *g_out, int *block_out, int32_t *flags_out) {
     // Launch shape: one workgroup for small n, else a co-resident group of
     // a few large workgroups (each merge costs every workgroup one agent-scope
     // release/acquire pair, so fewer workgroups mean a cheaper exchange).
@@ -688,6 +620,130 @@ int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     } else if (c->opt_defer == 2 && !(flags & HAC_MODE_SCAN)) {
         run_flags |= hac::kFlagDefer;  // one workgroup, deferred rescans on request
     }
+
+    // Deferred rescans pay on every group of workgroups (measured at n = 2048
+    // … 65536); a workgroup alone does better rescanning at once.
+    if (c->opt_defer == 1 && g < kDeferMinGroup) run_flags &= ~hac::kFlagDefer;
+    *g_out = g;
+    *block_out = block;
+    *flags_out = run_flags;
+    return HAC_OK;
+}
+
+// hac_run through the round engine (single and complete linkage).
+int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags, hipStream_t s) {
+    if (!c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
+    int G = c->cus * hac::rounds_occupancy();
+    if (c->opt_wgs > 0) G = std::min(G, (int)c->opt_wgs);
+    // Automatic mode: the one-merge-per-step kernel is queued behind the
+    // round engine and makes the remaining merges if the round engine hands
+    // them over (when rounds merge few pairs each, see hac_rounds.h).
+    const bool handover = c->opt_rounds == 1;
+    int g = 1, block = hac::kRunBlock;
+    int32_t seq_flags = 0;
+    int rc = HAC_OK;
+    if (handover) {
+        rc = plan_seq(c, n, flags, false, &g, &block, &seq_flags);
+        if (rc) return rc;
+    }
+    // Workspace: control | status | first upper row minima (set-up kernel) |
+    // round engine | exchange slots of the queued kernel.
+    const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
+    const size_t st_off = ctl_bytes, st_bytes = kAlign;
+    const size_t rk_off = st_off + st_bytes, rk_bytes = align_up((size_t)n * 8, kAlign);
+    const size_t ro_off = rk_off + rk_bytes;
+    const hac::RoundsLayout Lo = hac::rounds_layout(n, G);
+    const size_t sl_off = ro_off + Lo.bytes;
+    const size_t sl_bytes = (handover && g > 1) ? (size_t)2 * (g + 1) * hac::kSlotStride * 8 : 0;
+    rc = ensure_dev(c, &c->ws, &c->ws_cap, sl_off + sl_bytes, "workspace");
+    if (rc) return rc;
+    rc = ensure_pinned(c, ctl_bytes + kAlign);
+    if (rc) return rc;
+    char *ws = reinterpret_cast<char *>(c->ws);
+    float *D = dist;
+    if (flags & HAC_PRESERVE_INPUT) {
+        const size_t bytes = (size_t)n * n * 4;
+        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dcopy), &c->dcopy_cap, bytes, "input copy");
+        if (rc) return rc;
+        D = c->dcopy;
+    }
+    hac_merge *dev_out = out;
+    if (!(flags & HAC_OUT_DEVICE)) {
+        size_t cap_bytes = c->dout_cap * sizeof(hac_merge);
+        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dout), &cap_bytes, (size_t)(n - 1) * sizeof(hac_merge),
+                        "merge buffer");
+        if (rc) return rc;
+        c->dout_cap = cap_bytes / sizeof(hac_merge);
+        dev_out = c->dout;
+    }
+    hac::Instance inst{};
+    inst.D = D;
+    inst.out = dev_out;
+    inst.rowkey = reinterpret_cast<uint64_t *>(ws + rk_off);
+    inst.status = reinterpret_cast<uint32_t *>(ws + st_off);
+    inst.n = n;
+    inst.link = linkage;
+    HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
+    HIP_TRY(c, hac::launch_zero(ws + ro_off + Lo.ctl, sizeof(hac::RoundsCtl) / 4, s));
+    if (sl_bytes) HIP_TRY(c, hac::launch_zero(ws + sl_off, sl_bytes / 4, s));
+    HIP_TRY(c, hac::launch_setup(inst, dist, s));
+    HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    const int rflags = (c->opt_profile ? hac::kFlagProfile : 0) | (handover ? 0 : hac::kFlagNoHandover);
+    hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
+    hipError_t e = hac::launch_rounds(D, n, linkage, inst.status, ctl, ws + ro_off, G, timeout_ticks(c), rflags, s);
+    if (e != hipSuccess) return hip_fail(c, e, "round kernel launch");
+    if (handover) {
+        // Resumes from the round engine's state if it hands over; its
+        // records join the round engine's before they are sorted.
+        hac::Instance seq = inst;
+        seq.out = hac::rounds_records(n, G, ws + ro_off);
+        seq.slots = reinterpret_cast<uint64_t *>(ws + sl_off);
+        seq.exchange = (int32_t)c->opt_exchange;
+        seq.flags = seq_flags | hac::kFlagAfterRounds;
+        e = hac::launch_merge(seq, g, block, ctl, timeout_ticks(c), s, hac::rounds_resume(n, G, ws + ro_off));
+        if (e != hipSuccess) return hip_fail(c, e, "merge kernel launch");
+    }
+    e = hac::launch_rank(n, dev_out, inst.status, ws + ro_off, G, s);
+    if (e != hipSuccess) return hip_fail(c, e, "record sort launch");
+    HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    c->pending_wgs = G;
+    c->pending_block = hac::kRoundsBlock;
+    c->pending_group = G;
+    c->pending_graph = 0;
+    c->pending_deferred = 0;
+    c->pending_rounds = true;
+    c->pending_seq_wgs = g;
+    c->pending_seq_block = block;
+    c->pending_seq_deferred = (seq_flags & hac::kFlagDefer) ? 1 : 0;
+    return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
+}
+
+// hac_run and hac_run_noalloc.  noalloc: the device scratch is the static
+// array (c->scratch) instead of the context's workspace, the merge kernel
+// runs on at most HAC_NOALLOC_MAX_WORKGROUPS workgroups, out is device
+// memory, and nothing is allocated (the caller has rejected
+// HAC_PRESERVE_INPUT).
+int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags, void *stream,
+             bool noalloc) {
+    int rc = set_device(c);
+    if (rc) return rc;
+    if (c->pending) {
+        rc = hac_sync(c);
+        (void)rc;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    c->stats = hac_stats{};
+    c->pending_rounds = false;
+    if (n == 1) return HAC_OK;
+    if (!noalloc && !(flags & HAC_MODE_SCAN) && (linkage == HAC_SINGLE || linkage == HAC_COMPLETE) &&
+        (c->opt_rounds == 2 || (c->opt_rounds == 1 && n >= kRoundsMinN)))
+        return run_rounds(c, dist, n, linkage, out, flags, s);
+
+    int g = 1, block = hac::kRunBlock;
+    int32_t run_flags = 0;
+    rc = plan_seq(c, n, flags, noalloc, &g, &block, &run_flags);
+    if (rc) return rc;
 
     // Workspace: control | status | first row minima | slots.
     const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
@@ -737,9 +793,6 @@ int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     inst.n = n;
     inst.link = linkage;
     inst.exchange = (int32_t)c->opt_exchange;
-    // Deferred rescans pay on every group of workgroups (measured at n = 2048
-    // … 65536); a workgroup alone does better rescanning at once.
-    if (c->opt_defer == 1 && g < kDeferMinGroup) run_flags &= ~hac::kFlagDefer;
     inst.flags = run_flags;
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
 

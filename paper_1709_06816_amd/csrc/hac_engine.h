@@ -21,6 +21,8 @@ enum : uint32_t {
     kErrInput = 1u,     // non-finite or out-of-range input
     kErrTimeout = 2u,   // a wait exceeded the watchdog
     kErrInternal = 4u,  // no live pair found although >= 2 clusters remain
+    kHandover = 8u,     // not an error: the round engine left the instance to the
+                        // one-merge-per-step kernel queued behind it
 };
 
 // Phases timed by each workgroup (device wall clock).
@@ -63,6 +65,19 @@ enum : int32_t {
     kFlagScan = 2,     // no cached row minima: every merge rescans every live row (Section 5.3 step 1)
     kFlagDefer = 4,    // rows whose partner merged keep a lower bound and are rescanned while
                        // their workgroup waits in the next exchange (single instance, g > 1)
+    kFlagAfterRounds = 8,  // k_run queued behind the round engine: runs only on kHandover
+    kFlagNoHandover = 16,  // round engine: never hand over, rounds to the end (HAC_OPT_ROUNDS = 2)
+};
+
+// State left by the round engine when it hands an instance over part-way
+// (kHandover): the one-merge-per-step kernel queued behind it
+// resumes from it and writes its records, with their sort keys, after the
+// round engine's.  All pointers null: a run from the start.
+struct Resume {
+    const uint32_t *live;    // n-bit live mask
+    const int32_t *size;     // cluster size of every live slot
+    uint64_t *keys;          // sort key of every record: ord(h):32 | i:16 | round:16
+    const uint32_t *state;   // [0] merges done, [1] rounds run
 };
 
 // Rows a workgroup owns when g workgroups share n items.
@@ -85,6 +100,11 @@ hipError_t launch_setup(const Instance &inst, const float *src, hipStream_t stre
 // is recorded on the stream between the two.
 hipError_t launch_run(const Instance &inst, const float *src, int g, int block, Control *ctl,
                       uint64_t timeout_ticks, hipStream_t stream, hipEvent_t setup_done);
+// The merge kernel alone, after launch_setup has run on inst (queued behind
+// the round engine: kFlagAfterRounds in inst.flags, `rs` its hand-over
+// state, inst.out its record array).
+hipError_t launch_merge(const Instance &inst, int g, int block, Control *ctl, uint64_t timeout_ticks,
+                        hipStream_t stream, const Resume &rs = Resume{});
 
 // A batch launch: `count` instances in the order of `order` (device
 // int32[count], largest first); the first `ngroups` of them run on fixed

@@ -517,7 +517,8 @@ enum : int { kLoopCached = 0, kLoopDefer = 1, kLoopScan = 2 };
 
 template <int B, int kMode>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
-                           uint64_t timeout, Stats &st, uint32_t epoch0) {
+                           uint64_t timeout, Stats &st, uint32_t epoch0, int s0 = 0, uint64_t *keys = nullptr,
+                           int round0 = 0) {
     constexpr int W = B / 64;
     constexpr int U = upd_batch<B>();
     constexpr bool scan = kMode == kLoopScan, defer = kMode == kLoopDefer;
@@ -540,7 +541,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[(e + 1) & 1][0]);
     barrier_stores_done();  // later candidates are folded inside the update loop
     int i_prev = -1;
-    for (int s = 0; s < n - 1; ++s) {
+    for (int s = s0; s < n - 1; ++s) {
         // ---- argmin over the group (Section 5.3 steps 1-5) ---------------
         ++e;
         int b = e & 1;
@@ -626,6 +627,10 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             rec.z = __float_as_int(h);
             rec.w = ni + nj;
             reinterpret_cast<int4 *>(I.out)[s] = rec;
+            // After a hand-over each merge is the global minimum of its state,
+            // like one round of the round engine: its sort key continues the
+            // round count.
+            if (keys) keys[s] = ((uint64_t)ord32(h) << 32) | ((uint64_t)i << 16) | (uint64_t)(round0 + (s - s0));
         }
         if (s == n - 2) break;
 
@@ -825,25 +830,54 @@ __global__ __launch_bounds__(kSetupBlock) void k_setup(Instance I, const float *
 }
 
 template <int B, int kMode>
-__global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t timeout) {
+__global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t timeout, Resume rs) {
     extern __shared__ __align__(16) uint8_t smem[];
     Stats st;
     if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
     const int g = (int)gridDim.x, w = (int)blockIdx.x, n = I.n;
     const int own_cap = ((((n + 63) >> 6) + g - 1) / g) * 64;
     const Lds L = carve(smem, n, own_cap);
-    // The set-up kernel has finished: its status word is final and the same
-    // for every thread of every workgroup.
-    if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
-    init_masks<B>(L, n);
+    // The set-up kernel (and the round engine, if queued behind it) has
+    // finished: the status word is final and the same for every thread of
+    // every workgroup.
+    const uint32_t st0 = __hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st0 & kErrInput) return;
+    if ((I.flags & kFlagAfterRounds) && !(st0 & kHandover)) return;
     const int own_ch = own_chunks(n, g, w);
-    for (int li = threadIdx.x; li < own_cap; li += B) {
-        const int k = row_of_local(li, g, w);
-        const uint64_t v = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmpty;
-        L.cache[li] = v == kEmpty ? kEmptyRow : v;
+    if (!(I.flags & kFlagAfterRounds)) {
+        init_masks<B>(L, n);
+        for (int li = threadIdx.x; li < own_cap; li += B) {
+            const int k = row_of_local(li, g, w);
+            const uint64_t v = (li < own_ch * 64 && k < n) ? I.rowkey[k] : kEmpty;
+            L.cache[li] = v == kEmpty ? kEmptyRow : v;
+        }
+        __syncthreads();
+        merge_loop<B, kMode>(I, g, w, L, ctl, timeout, st, 0u);
+    } else {
+        // Resume where the round engine stopped: its live slots and sizes,
+        // and every own live row's minimum over the live columns to its
+        // right, rescanned from the current matrix.
+        const int s0 = (int)rs.state[0], round0 = (int)rs.state[1];
+        const int mask_words = (n + 31) >> 5;
+        for (int q = threadIdx.x; q < mask_words; q += B) L.amask[q] = rs.live[q];
+        for (int k = threadIdx.x; k < n; k += B) L.size1[k] = (uint16_t)(rs.size[k] - 1);
+        if (threadIdx.x == 0) s_nresc = 0;
+        __syncthreads();
+        for (int li = threadIdx.x; li < own_cap; li += B) {
+            const int k = row_of_local(li, g, w);
+            L.cache[li] = kEmptyRow;
+            if (li < own_ch * 64 && k < n && is_live(L.amask, k)) L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
+        }
+        __syncthreads();
+        rescan_rows<B>(I.D, n, g, w, L, s_nresc, -1, st.rescan_elems);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            st.rescans += s_nresc;
+            s_nresc = 0;
+        }
+        __syncthreads();
+        merge_loop<B, kMode>(I, g, w, L, ctl, timeout, st, 0u, s0, rs.keys, round0);
     }
-    __syncthreads();
-    merge_loop<B, kMode>(I, g, w, L, ctl, timeout, st, 0u);
     flush_stats<B>(ctl, st);
 }
 
@@ -1277,11 +1311,17 @@ hipError_t launch_run(const Instance &inst, const float *src, int g, int block, 
         e = hipEventRecord(setup_done, stream);
         if (e != hipSuccess) return e;
     }
+    return launch_merge(inst, g, block, ctl, timeout_ticks, stream);
+}
+
+hipError_t launch_merge(const Instance &inst, int g, int block, Control *ctl, uint64_t timeout_ticks,
+                        hipStream_t stream, const Resume &rs) {
     const size_t lds = lds_bytes(inst.n, own_rows(inst.n, g), false);
     Instance a0 = inst;
     Control *a1 = ctl;
     uint64_t a2 = timeout_ticks;
-    void *args[] = {&a0, &a1, &a2};
+    Resume a3 = rs;
+    void *args[] = {&a0, &a1, &a2, &a3};
     const int mode = (inst.flags & kFlagScan) ? kLoopScan : (inst.flags & kFlagDefer) ? kLoopDefer : kLoopCached;
     if (g == 1) return hipLaunchKernel(run_kernel(block, mode), dim3(1), dim3(block), args, lds, stream);
     return hipLaunchCooperativeKernel(run_kernel(block, mode), dim3(g), dim3(block), args, (unsigned)lds, stream);

@@ -141,11 +141,32 @@ __device__ T block_min(T v) {
     return r;
 }
 
-// One wave recomputes row r's cache entry over the live columns other than
-// r: rk[r] = ord(min):32 | smallest column attaining it:16, cnt[r] = number
-// of live columns attaining it (kNone / 0 if no live column is left).
-__device__ void rescan_row(const float *__restrict__ D, int n, int r, uint64_t *rk, int32_t *cnt,
-                           unsigned long long &elems) {
+// Rescans are cut into segments of kSeg columns, one wave each, so that a
+// row is rescanned by many waves at once.  A segment folds its result into
+// the row's words with atomics: rk[r] = ord(min):32 | smallest column
+// attaining it:16 (atomic minimum), cw[r] = ord(min):32 | number of columns
+// attaining it:32 (the smaller value wins, equal values add their counts).
+// Both start from kNone / kNoCount.
+constexpr int kSeg = 2048;
+constexpr uint64_t kNoCount = 0xFFFFFFFF00000000ull;
+
+__device__ void fold_count(uint64_t *cw, uint32_t v, uint32_t c) {
+    unsigned long long *q = reinterpret_cast<unsigned long long *>(cw);
+    unsigned long long cur = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const uint32_t cv = (uint32_t)(cur >> 32);
+        if (v > cv) return;
+        const unsigned long long nv = v < cv ? (((unsigned long long)v << 32) | c) : cur + c;
+        if (__hip_atomic_compare_exchange_strong(q, &cur, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+    }
+}
+
+// One wave: minimum and its count over the live columns c != r of segment
+// `seg` of row r, folded into rk[r] and cw[r].
+__device__ void rescan_segment(const float *__restrict__ D, int n, int r, int seg, uint64_t *rk, uint64_t *cw,
+                               unsigned long long &elems) {
     const int lane = threadIdx.x & 63;
     const float *row = D + (size_t)r * n;
     uint32_t mv = 0xFFFFFFFFu;
@@ -161,58 +182,57 @@ __device__ void rescan_row(const float *__restrict__ D, int n, int r, uint64_t *
         }
         ++elems;
     };
+    const int c0 = seg * kSeg, c1 = min(n, c0 + kSeg);
     if ((n & 3) == 0) {
-        constexpr int U = 8;
-        const int nq = n >> 2;
-        for (int q0 = 0; q0 < nq; q0 += 64 * U) {
-            float4 x[U];
+        constexpr int U = kSeg / 256;  // 16-byte loads per lane
+        float4 x[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int q = q0 + u * 64 + lane;
-                x[u] = q < nq ? *reinterpret_cast<const float4 *>(row + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + 4 * (u * 64 + lane);
+            x[u] = c < c1 ? *reinterpret_cast<const float4 *>(row + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int q = q0 + u * 64 + lane;
-                if (q >= nq) continue;
-                uint32_t m = (s_live[q >> 3] >> ((q & 7) * 4)) & 0xFu;
-                if ((r >> 2) == q) m &= ~(1u << (r & 3));
-                if (!m) continue;
-                if (m & 1u) take(x[u].x, 4 * q);
-                if (m & 2u) take(x[u].y, 4 * q + 1);
-                if (m & 4u) take(x[u].z, 4 * q + 2);
-                if (m & 8u) take(x[u].w, 4 * q + 3);
-            }
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + 4 * (u * 64 + lane);
+            if (c >= c1) continue;
+            const int q = c >> 2;
+            uint32_t m = (s_live[q >> 3] >> ((q & 7) * 4)) & 0xFu;
+            if ((r >> 2) == q) m &= ~(1u << (r & 3));
+            if (!m) continue;
+            if (m & 1u) take(x[u].x, c);
+            if (m & 2u) take(x[u].y, c + 1);
+            if (m & 4u) take(x[u].z, c + 2);
+            if (m & 8u) take(x[u].w, c + 3);
         }
     } else {
         constexpr int U = 8;
-        for (int c0 = 0; c0 < n; c0 += 64 * U) {
+        for (int b0 = c0; b0 < c1; b0 += 64 * U) {
             float x[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int c = c0 + u * 64 + lane;
-                x[u] = c < n ? row[c] : 0.0f;
+                const int c = b0 + u * 64 + lane;
+                x[u] = c < c1 ? row[c] : 0.0f;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int c = c0 + u * 64 + lane;
-                if (c < n && c != r && live_at(c)) take(x[u], c);
+                const int c = b0 + u * 64 + lane;
+                if (c < c1 && c != r && live_at(c)) take(x[u], c);
             }
         }
     }
     const uint64_t mine = mn ? (((uint64_t)mv << 32) | ((uint64_t)mc << 16)) : kNone;
     const uint64_t best = wave_min(mine);
     const unsigned long long ties = wave_sum((mn && mv == value_of(best)) ? (unsigned long long)mn : 0ull);
-    if (lane == 0) {
-        rk[r] = best;
-        cnt[r] = (int32_t)ties;
+    if (lane == 0 && best != kNone) {
+        atomicMin(reinterpret_cast<unsigned long long *>(rk + r), (unsigned long long)best);
+        fold_count(cw + r, value_of(best), (uint32_t)ties);
     }
 }
 
 struct Views {
     RoundsCtl *rc;
-    uint64_t *rk;      // n row entries
-    int32_t *cnt;      // n counts of entries equal to the row minimum
+    uint64_t *rk;      // n row entries ord(min):32 | partner:16
+    uint64_t *cw;      // n words ord(min):32 | count of entries equal to the minimum:32
     int32_t *size;     // n cluster sizes
     int32_t *role;     // n: +(p+1) survivor of pair p this round, -(p+1) retired, 0 otherwise
     int32_t *resc;     // rows queued for a rescan this round
@@ -220,13 +240,14 @@ struct Views {
     uint64_t *k1;      // G smallest pair keys (one per workgroup)
     int4 *rec;         // n-1 records in claim order
     uint64_t *key;     // their sort keys ord(h):32 | i:16 | round:16
+    uint32_t *live;    // live mask left at a hand-over
 };
 
 __device__ Views views(char *ws, const RoundsLayout &Lo) {
     Views v;
     v.rc = reinterpret_cast<RoundsCtl *>(ws + Lo.ctl);
     v.rk = reinterpret_cast<uint64_t *>(ws + Lo.rk);
-    v.cnt = reinterpret_cast<int32_t *>(ws + Lo.cnt);
+    v.cw = reinterpret_cast<uint64_t *>(ws + Lo.cnt);
     v.size = reinterpret_cast<int32_t *>(ws + Lo.size);
     v.role = reinterpret_cast<int32_t *>(ws + Lo.role);
     v.resc = reinterpret_cast<int32_t *>(ws + Lo.resc);
@@ -234,12 +255,45 @@ __device__ Views views(char *ws, const RoundsLayout &Lo) {
     v.k1 = reinterpret_cast<uint64_t *>(ws + Lo.k1);
     v.rec = reinterpret_cast<int4 *>(ws + Lo.rec);
     v.key = reinterpret_cast<uint64_t *>(ws + Lo.key);
+    v.live = reinterpret_cast<uint32_t *>(ws + Lo.live);
     return v;
 }
 
-__global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int link, const uint32_t *status,
-                                                         Control *ctl, char *ws, RoundsLayout Lo, uint64_t timeout) {
+__device__ __forceinline__ uint32_t count_of(uint64_t w) { return (uint32_t)w; }
+
+// Wall clock of thread 0 charged to phases (kFlagProfile): [0] first
+// rescans, [1] waiting at grid barriers, [2] phase B, [3] phase C, [4] phase A.
+struct Clock {
+    bool on;
+    uint64_t mark = 0;
+    unsigned long long t[kPhases] = {0, 0, 0, 0, 0};
+    __device__ void lap(int p) {
+        if (on && threadIdx.x == 0) {
+            const uint64_t now = wall_clock64();
+            t[p] += now - mark;
+            mark = now;
+        }
+    }
+};
+
+// The round engine hands the remaining merges over to the one-merge-per-step
+// kernel queued behind it when the last kWindow rounds merged fewer than
+// kWindow * kMinPerRound pairs: a round (three grid barriers) then costs more
+// than the merges it makes would cost one exchange each.  That happens near
+// the end of every run, when few clusters are left, and, for single linkage
+// on input with many equal values, early: strict pairs become rare as
+// clusters grow.  Each merge after the hand-over is the smallest key of its
+// state, as the smallest key of a round is, so the records keep their order
+// under (h, i, round).
+constexpr int kWindow = 8;
+constexpr int kMinPerRound = 12;
+
+__global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int link, uint32_t *status,
+                                                         Control *ctl, char *ws, RoundsLayout Lo, uint64_t timeout,
+                                                         int flags) {
     const Views V = views(ws, Lo);
+    Clock clk{(flags & kFlagProfile) != 0};
+    if (clk.on && threadIdx.x == 0) clk.mark = wall_clock64();
     const uint32_t G = gridDim.x;
     const int w = (int)blockIdx.x, tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int gw = w * W + wv, NW = (int)G * W;
@@ -255,21 +309,46 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
     for (int k = w * B + tid; k < n; k += (int)G * B) {
         V.size[k] = 1;
         V.role[k] = 0;
+        V.rk[k] = kNone;
+        V.cw[k] = kNoCount;
     }
     __syncthreads();
-    // First cache entries: every row's minimum over the whole row.
-    for (int r = gw; r < n; r += NW) {
-        rescan_row(D, n, r, V.rk, V.cnt, st_resc);
-        ++st_rows;
-    }
     uint32_t gen = 0;
     if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+    const int nseg = (n + kSeg - 1) / kSeg;
+    // First cache entries: every row's minimum over the whole row.
+    for (int t = gw; t < n * nseg; t += NW) {
+        rescan_segment(D, n, t / nseg, t % nseg, V.rk, V.cw, st_resc);
+        st_rows += (t % nseg) == 0;
+    }
+    clk.lap(0);
+    if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+    clk.lap(1);
 
     const int R = (n + (int)G - 1) / (int)G;  // rows per workgroup in phase A
     const int r0 = w * R, r1 = min(n, r0 + R);
+    const bool may_hand_over = !(flags & kFlagNoHandover);
+    int window[kWindow] = {0};  // merges of the last kWindow rounds
     const int nblocks = (n + 63) >> 6;
     int merges = 0, round = 0;
     while (merges < n - 1) {
+        if (may_hand_over && round >= kWindow) {
+            int recent = 0;
+#pragma unroll
+            for (int t = 0; t < kWindow; ++t) recent += window[t];
+            if (recent < kWindow * kMinPerRound) {
+                // Leave the state to the kernel queued behind this one.
+                if (w == 0) {
+                    for (int q = tid; q < words; q += B) V.live[q] = s_live[q];
+                    if (tid == 0) {
+                        V.rc->merges = (uint32_t)merges;
+                        V.rc->round = (uint32_t)round;
+                        atomicOr(status, kHandover);
+                    }
+                }
+                break;
+            }
+        }
         // ---- A: claim reciprocal (single: and strict) pairs -------------
         if (w == 0 && tid == 0) V.rc->resc = 0;
         uint64_t kmin = kNone;
@@ -283,7 +362,7 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
             if (a > b) continue;
             const uint64_t eb = V.rk[b];
             if (partner_of(eb) != a) continue;
-            if (link == HAC_SINGLE && (V.cnt[a] != 1 || V.cnt[b] != 1)) continue;
+            if (link == HAC_SINGLE && (count_of(V.cw[a]) != 1u || count_of(V.cw[b]) != 1u)) continue;
             const uint32_t slot = atomicAdd(&V.rc->pairs, 1u);
             if (slot >= (uint32_t)kRoundsMaxPairs) continue;
             V.pairs[slot] = make_int2(a, b);
@@ -294,7 +373,9 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
         }
         kmin = block_min(kmin);
         if (tid == 0) V.k1[w] = kmin;
+        clk.lap(4);
         if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+        clk.lap(1);
 
         // ---- B: Lance-Williams updates of every pair --------------------
         {
@@ -318,11 +399,11 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
                     if (V.role[ka] <= 0) {
                         s_pair[p0] = make_int2(ka, kb);
                         np = p0 + 1;
-                        if (w == 0)
+                        if (w == 0) {
                             V.rec[merges + p0] = make_int4(ka, kb, __float_as_int(unord32((uint32_t)(k1 >> 32))),
                                                            V.size[ka] + V.size[kb]);
-                        if (w == 0)
                             V.key[merges + p0] = (k1 & 0xFFFFFFFF00000000ull) | ((uint64_t)ka << 16) | (uint64_t)round;
+                        }
                     }
                 }
                 s_np = np;
@@ -331,6 +412,12 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
             __syncthreads();
             const int np = s_np;
             if (np < 0) return;
+            // The survivors' rows are rescanned in phase C: clear their words.
+            if (w == 0)
+                for (int t = tid; t < np; t += B) {
+                    V.rk[s_pair[t].x] = kNone;
+                    V.cw[s_pair[t].x] = kNoCount;
+                }
             const int extra_i = np > p0 ? s_pair[p0].x : -1, extra_j = np > p0 ? s_pair[p0].y : -1;
             const int npr = (np + kPairsPerUnit - 1) / kPairsPerUnit;
             const int units = nblocks * npr;
@@ -369,12 +456,18 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
                             D[(size_t)c * n + ij.x] = v;
                             ++st_upd;
                             if (link == HAC_COMPLETE) {
-                                if (pic == ij.x || pic == ij.y) V.resc[atomicAdd(&V.rc->resc, 1u)] = c;
+                                if (pic == ij.x || pic == ij.y) {
+                                    // The row's minimum went up or away: rescan it.
+                                    V.rk[c] = kNone;
+                                    V.cw[c] = kNoCount;
+                                    V.resc[atomicAdd(&V.rc->resc, 1u)] = c;
+                                }
                             } else {
                                 if (ord32(v) == valc)
                                     atomicMin(reinterpret_cast<unsigned long long *>(V.rk + c),
                                               (unsigned long long)(((uint64_t)valc << 32) | ((uint64_t)ij.x << 16)));
-                                if (ord32(a[t]) == valc && ord32(b[t]) == valc) atomicSub(V.cnt + c, 1);
+                                if (ord32(a[t]) == valc && ord32(b[t]) == valc)
+                                    atomicSub(reinterpret_cast<unsigned long long *>(V.cw + c), 1ull);
                             }
                         } else {
                             // Column c is i_q or j_q of another pair q: its part of
@@ -387,7 +480,9 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
                 }
             }
         }
+        clk.lap(2);
         if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+        clk.lap(1);
 
         // ---- C: retire, rescan survivors and rows whose partner merged --
         {
@@ -410,17 +505,23 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
             const int nr = link == HAC_COMPLETE
                                ? (int)__hip_atomic_load(&V.rc->resc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                : 0;
-            for (int t = gw; t < np + nr; t += NW) {
-                const int r = t < np ? s_pair[t].x : V.resc[t - np];
-                rescan_row(D, n, r, V.rk, V.cnt, st_resc);
-                ++st_rows;
+            const int items = (np + nr) * nseg;
+            for (int t = gw; t < items; t += NW) {
+                const int k = t / nseg;
+                const int r = k < np ? s_pair[k].x : V.resc[k - np];
+                rescan_segment(D, n, r, t % nseg, V.rk, V.cw, st_resc);
+                st_rows += (t % nseg) == 0;
             }
             merges += np;
+            window[round % kWindow] = np;
             ++round;
         }
+        clk.lap(3);
         if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+        clk.lap(1);
     }
-    // Statistics (rows rescanned counts waves, so only lane 0's count).
+    // Statistics (rows rescanned are counted by the wave of their first
+    // segment, so only lane 0's count).
     const unsigned long long rows = wave_sum(lane == 0 ? st_rows : 0ull);
     const unsigned long long re = wave_sum(st_resc);
     const unsigned long long up = wave_sum(st_upd);
@@ -430,6 +531,12 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
         atomicAdd(&ctl->update_elems, up);
     }
     if (w == 0 && tid == 0) ctl->rounds = (uint32_t)round;
+    if (clk.on && tid == 0) {
+        for (int p = 0; p < kPhases; ++p) {
+            atomicAdd(&ctl->prof_sum[p], clk.t[p]);
+            atomicMax(&ctl->prof_max[p], clk.t[p]);
+        }
+    }
 }
 
 // Records in merge order: record r goes to the rank of its key among all
@@ -460,7 +567,7 @@ RoundsLayout rounds_layout(int n, int G) {
     size_t off = 0;
     L.ctl = off;   off += al(sizeof(RoundsCtl));
     L.rk = off;    off += al((size_t)n * 8);
-    L.cnt = off;   off += al((size_t)n * 4);
+    L.cnt = off;   off += al((size_t)n * 8);
     L.size = off;  off += al((size_t)n * 4);
     L.role = off;  off += al((size_t)n * 4);
     L.resc = off;  off += al((size_t)n * 4);
@@ -468,6 +575,7 @@ RoundsLayout rounds_layout(int n, int G) {
     L.k1 = off;    off += al((size_t)G * 8);
     L.rec = off;   off += al((size_t)(n > 1 ? n - 1 : 1) * 16);
     L.key = off;   off += al((size_t)(n > 1 ? n - 1 : 1) * 8);
+    L.live = off;  off += al((size_t)((n + 31) / 32) * 4);
     L.bytes = off;
     return L;
 }
@@ -482,26 +590,45 @@ int rounds_occupancy() {
     return blocks < 1 ? 1 : blocks;
 }
 
-hipError_t launch_rounds(float *D, int n, int link, hac_merge *out, const uint32_t *status, Control *ctl, void *ws,
-                         int G, uint64_t timeout_ticks, hipStream_t stream) {
+hipError_t launch_rounds(float *D, int n, int link, uint32_t *status, Control *ctl, void *ws, int G,
+                         uint64_t timeout_ticks, int flags, hipStream_t stream) {
     const RoundsLayout Lo = rounds_layout(n, G);
     float *a0 = D;
     int a1 = n;
     int a2 = link;
-    const uint32_t *a3 = status;
+    uint32_t *a3 = status;
     Control *a4 = ctl;
     char *a5 = static_cast<char *>(ws);
     RoundsLayout a6 = Lo;
     uint64_t a7 = timeout_ticks;
-    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
-    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_rounds), dim3(G), dim3(kRoundsBlock),
-                                              args, 0, stream);
-    if (e != hipSuccess) return e;
+    int a8 = flags;
+    void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_rounds), dim3(G), dim3(kRoundsBlock), args, 0,
+                                      stream);
+}
+
+hipError_t launch_rank(int n, hac_merge *out, const uint32_t *status, void *ws, int G, hipStream_t stream) {
+    const RoundsLayout Lo = rounds_layout(n, G);
     const int m = n - 1;
     hipLaunchKernelGGL(k_rank, dim3((m + 255) / 256), dim3(256), 0, stream,
                        reinterpret_cast<const int4 *>(static_cast<char *>(ws) + Lo.rec),
                        reinterpret_cast<const uint64_t *>(static_cast<char *>(ws) + Lo.key), m, out, status);
     return hipGetLastError();
+}
+
+Resume rounds_resume(int n, int G, void *ws) {
+    const RoundsLayout Lo = rounds_layout(n, G);
+    char *b = static_cast<char *>(ws);
+    Resume r;
+    r.live = reinterpret_cast<const uint32_t *>(b + Lo.live);
+    r.size = reinterpret_cast<const int32_t *>(b + Lo.size);
+    r.keys = reinterpret_cast<uint64_t *>(b + Lo.key);
+    r.state = reinterpret_cast<const uint32_t *>(b + Lo.ctl + offsetof(RoundsCtl, merges));
+    return r;
+}
+
+hac_merge *rounds_records(int n, int G, void *ws) {
+    return reinterpret_cast<hac_merge *>(static_cast<char *>(ws) + rounds_layout(n, G).rec);
 }
 
 }  // namespace hac

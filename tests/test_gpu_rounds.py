@@ -58,7 +58,7 @@ def test_rounds_match_oracle(ctx, link, name, gen, n):
     got, st = _run(ctx, d, link)
     exp = oracle.run_f32(d, link)
     assert got.tobytes() == exp.tobytes()
-    assert st["rounds"] >= 1
+    assert st["rounds"] >= 1 and st["handed_over"] == 0
 
 
 @pytest.mark.parametrize("wgs", [1, 2, 7, 33])
@@ -121,3 +121,35 @@ def test_rounds_not_used_for_other_linkages(ctx):
     got = ctx.run(torch.from_numpy(d).cuda(), "average")
     assert ctx.stats()["rounds"] == 0
     assert got.tobytes() == oracle.run_f32(d, "average").tobytes()
+
+
+def test_single_linkage_hands_over_part_way(ctx):
+    """Automatic mode: rounds stop once they merge few pairs each and the
+    one-merge-per-step kernel queued behind resumes from that state (early for
+    single linkage on input with many equal values); every result is the
+    oracle's, on several workgroup counts."""
+    import torch
+    ctx.set_option(hac.OPT_ROUNDS, 1)
+    try:
+        for name, d, handed in (("quantized", synth.quantized_matrix(2000, seed=31, levels=6), True),
+                                ("rmsd_like", synth.rmsd_like(seed=33, n=3000), True),
+                                # n <= 1536: the resuming kernel is one workgroup
+                                ("quantized", synth.quantized_matrix(1200, seed=34, levels=4), True),
+                                ("mixture", synth.mixture_8192(seed=32, n=2000), False)):
+            for wgs in (0, 5):
+                ctx.set_option(hac.OPT_WORKGROUPS, wgs)
+                print("rounds: automatic single %s n=%d wgs=%d" % (name, d.shape[0], wgs), flush=True)
+                got = ctx.run(torch.from_numpy(d).cuda(), "single")
+                st = ctx.stats()
+                if handed:
+                    # Ties force it early (untied input may hand over only the tail).
+                    assert st["handed_over"] == 1 and st["rounds"] < 200, (name, st)
+                assert st["rounds"] > 0
+                assert got.tobytes() == oracle.run_f32(d, "single").tobytes()
+            ctx.set_option(hac.OPT_WORKGROUPS, 0)
+            got = ctx.run(torch.from_numpy(d).cuda(), "complete")
+            assert ctx.stats()["rounds"] > 0
+            assert got.tobytes() == oracle.run_f32(d, "complete").tobytes()
+    finally:
+        ctx.set_option(hac.OPT_ROUNDS, 2)
+        ctx.set_option(hac.OPT_WORKGROUPS, 0)
