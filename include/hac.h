@@ -257,6 +257,12 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        rounds to the end.  Not
  *                        used by hac_run_noalloc, HAC_MODE_SCAN or other
  *                        linkages.
+ *   HAC_OPT_INJECT_STALL failure test: 1 = in every following hac_run that runs
+ *                        on several workgroups, workgroup 0 never publishes its
+ *                        first exchange, so the other workgroups' bounded waits
+ *                        expire after HAC_OPT_TIMEOUT_MS, every workgroup leaves
+ *                        the kernel and the call returns HAC_ETIMEDOUT (out
+ *                        unspecified).  0 (the default) = off.
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
@@ -270,7 +276,8 @@ typedef enum {
     HAC_OPT_BATCH_GROUP = 9,
     HAC_OPT_GRAPH = 10,
     HAC_OPT_DEFER = 11,
-    HAC_OPT_ROUNDS = 12
+    HAC_OPT_ROUNDS = 12,
+    HAC_OPT_INJECT_STALL = 13
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 

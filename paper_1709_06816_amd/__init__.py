@@ -39,6 +39,7 @@ OPT_WORKGROUPS, OPT_SINGLE_WG_N, OPT_TIMEOUT_MS, OPT_EXCHANGE, OPT_PROFILE, OPT_
 OPT_AUTOTUNE, OPT_BATCH_BLOCK, OPT_BATCH_GROUP, OPT_GRAPH = 7, 8, 9, 10
 OPT_DEFER = 11
 OPT_ROUNDS = 12
+OPT_INJECT_STALL = 13
 MAX_N = 65536
 MAX_BATCH_N = 8192
 NOALLOC_MAX_N = 65536

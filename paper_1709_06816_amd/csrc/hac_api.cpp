@@ -16,6 +16,7 @@
 #include "hac_engine.h"
 #include "hac_rmsd.h"
 #include "hac_rounds.h"
+#include "hac_validate.h"
 
 namespace {
 
@@ -64,6 +65,7 @@ struct hac_ctx {
     int64_t opt_graph = 1;
     int64_t opt_defer = 1;
     int64_t opt_rounds = 1;
+    int64_t opt_stall = 0;
     std::unordered_map<std::string, hipGraphExec_t> graphs;  // batch graphs by layout
 
     // State of the last enqueued call, for hac_sync / stats.
@@ -76,6 +78,12 @@ struct hac_ctx {
 };
 
 namespace {
+
+// The message of a failed argument check becomes the context's last error.
+int checked(hac_ctx *c, int rc, const char *msg) {
+    if (rc != HAC_OK) c->err = msg;
+    return rc;
+}
 
 int fail(hac_ctx *c, int code, const char *fmt, ...) {
     if (c) {
@@ -500,12 +508,10 @@ int hac_destroy(hac_ctx *c) {
 int hac_rmsd(hac_ctx *c, const float *coords, int32_t n, int32_t atoms, float *dist, uint32_t flags, void *stream) {
     if (!c) return HAC_EINVAL;
     c->err.clear();
-    if (!coords || !dist) return fail(c, HAC_EINVAL, "coords or dist is NULL");
-    if (n < 1 || n > HAC_MAX_N) return fail(c, HAC_EINVAL, "n=%d outside 1..%d", n, HAC_MAX_N);
-    if (atoms < 1 || atoms > hac::kRmsdMaxAtoms)
-        return fail(c, HAC_EINVAL, "atoms=%d outside 1..%d", atoms, hac::kRmsdMaxAtoms);
-    if (flags != 0) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
-    int rc = set_device(c);
+    char msg[192];
+    int rc = hac::check_rmsd_args(coords, n, atoms, dist, flags, hac::kRmsdMaxAtoms, msg, sizeof msg);
+    if (rc) return checked(c, rc, msg);
+    rc = set_device(c);
     if (rc) return rc;
     if (c->pending) (void)hac_sync(c);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -544,6 +550,7 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
         return HAC_OK;
     case HAC_OPT_AUTOTUNE: c->opt_autotune = value != 0; return HAC_OK;
     case HAC_OPT_GRAPH: c->opt_graph = value != 0; return HAC_OK;
+    case HAC_OPT_INJECT_STALL: c->opt_stall = value != 0; return HAC_OK;
     case HAC_OPT_ROUNDS:
         if (value > 2) return fail(c, HAC_EINVAL, "rounds mode %lld is not 0, 1 or 2", (long long)value);
         c->opt_rounds = value;
@@ -595,7 +602,8 @@ int plan_seq(hac_ctx *c, int32_t n, uint32_t flags, bool noalloc, int *g_out, in
     const int block = c->opt_block > 0 ? (int)c->opt_block : hac::kRunBlock;
     const int single_n = c->opt_single_n > 0 ? (int)c->opt_single_n : kDefaultSingleWgN;
     int g = 1;
-    int32_t run_flags = (c->opt_profile ? hac::kFlagProfile : 0) | ((flags & HAC_MODE_SCAN) ? hac::kFlagScan : 0);
+    int32_t run_flags = (c->opt_profile ? hac::kFlagProfile : 0) | ((flags & HAC_MODE_SCAN) ? hac::kFlagScan : 0) |
+                        (c->opt_stall ? hac::kFlagStall : 0);
     if (n > single_n || hac::lds_bytes(n, hac::own_rows(n, 1), false) > c->lds_max) {
         // Co-residency is checked for the deferred variant too, which may
         // be chosen below once g is known.
@@ -689,7 +697,8 @@ int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *o
     if (sl_bytes) HIP_TRY(c, hac::launch_zero(ws + sl_off, sl_bytes / 4, s));
     HIP_TRY(c, hac::launch_setup(inst, dist, s));
     HIP_TRY(c, hipEventRecord(c->ev[1], s));
-    const int rflags = (c->opt_profile ? hac::kFlagProfile : 0) | (handover ? 0 : hac::kFlagNoHandover);
+    const int rflags = (c->opt_profile ? hac::kFlagProfile : 0) | (handover ? 0 : hac::kFlagNoHandover) |
+                       (c->opt_stall ? hac::kFlagStall : 0);
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
     hipError_t e = hac::launch_rounds(D, n, linkage, inst.status, ctl, ws + ro_off, G, timeout_ticks(c), rflags, s);
     if (e != hipSuccess) return hip_fail(c, e, "round kernel launch");
@@ -704,7 +713,7 @@ int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *o
         e = hac::launch_merge(seq, g, block, ctl, timeout_ticks(c), s, hac::rounds_resume(n, G, ws + ro_off));
         if (e != hipSuccess) return hip_fail(c, e, "merge kernel launch");
     }
-    e = hac::launch_rank(n, dev_out, inst.status, ws + ro_off, G, s);
+    e = hac::launch_rank(n, dev_out, inst.status, ctl, ws + ro_off, G, s);
     if (e != hipSuccess) return hip_fail(c, e, "record sort launch");
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     c->pending_wgs = G;
@@ -822,11 +831,10 @@ int hac_run(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out,
             void *stream) {
     if (!c) return HAC_EINVAL;
     c->err.clear();
-    if (!dist) return fail(c, HAC_EINVAL, "dist is NULL");
-    if (n < 1 || n > HAC_MAX_N) return fail(c, HAC_EINVAL, "n=%d outside 1..%d", n, HAC_MAX_N);
-    if (linkage < 0 || linkage > HAC_CENTROID) return fail(c, HAC_EINVAL, "linkage %d is not 0..5", linkage);
-    if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE | HAC_MODE_SCAN)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
-    if (n > 1 && !out) return fail(c, HAC_EINVAL, "out is NULL");
+    char msg[192];
+    int rc = hac::check_run_args(dist, n, linkage, out, flags, HAC_PRESERVE_INPUT | HAC_OUT_DEVICE | HAC_MODE_SCAN,
+                                 HAC_MAX_N, msg, sizeof msg);
+    if (rc) return checked(c, rc, msg);
     return run_impl(c, dist, n, linkage, out, flags, stream, false);
 }
 
@@ -834,15 +842,15 @@ int hac_run_noalloc(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_mer
                     void *stream) {
     if (!c) return HAC_EINVAL;
     c->err.clear();
-    if (!dist) return fail(c, HAC_EINVAL, "dist is NULL");
-    if (n < 1 || n > HAC_NOALLOC_MAX_N)
-        return fail(c, HAC_EINVAL, "n=%d outside 1..%d (the static scratch holds the row minima of at most %d items)",
-                    n, HAC_NOALLOC_MAX_N, HAC_NOALLOC_MAX_N);
-    if (linkage < 0 || linkage > HAC_CENTROID) return fail(c, HAC_EINVAL, "linkage %d is not 0..5", linkage);
     if (flags & HAC_PRESERVE_INPUT)
         return fail(c, HAC_EINVAL, "HAC_PRESERVE_INPUT needs an n*n workspace; hac_run_noalloc allocates none");
-    if (flags & ~(HAC_OUT_DEVICE | HAC_MODE_SCAN)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
-    if (n > 1 && !out) return fail(c, HAC_EINVAL, "out is NULL");
+    if (n > HAC_NOALLOC_MAX_N)
+        return fail(c, HAC_EINVAL, "n=%d outside 1..%d (the static scratch holds the row minima of at most %d items)",
+                    n, HAC_NOALLOC_MAX_N, HAC_NOALLOC_MAX_N);
+    char msg[192];
+    const int rc = hac::check_run_args(dist, n, linkage, out, flags, HAC_OUT_DEVICE | HAC_MODE_SCAN,
+                                       HAC_NOALLOC_MAX_N, msg, sizeof msg);
+    if (rc) return checked(c, rc, msg);
     if (!c->scratch) return fail(c, HAC_EDEVICE, "no static scratch on this device");
     return run_impl(c, dist, n, linkage, out, flags, stream, true);
 }
@@ -854,20 +862,12 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->err.clear();
     if (count < 0) return fail(c, HAC_EINVAL, "count=%d", count);
     if (count == 0) return HAC_OK;
-    if (!packed || !offsets || !ns || !linkages || !out || !out_offsets)
-        return fail(c, HAC_EINVAL, "NULL argument");
-    if (flags & ~(HAC_PRESERVE_INPUT | HAC_OUT_DEVICE)) return fail(c, HAC_EINVAL, "unknown flags 0x%x", flags);
     int64_t extent = 0, rec_extent = 0;
-    for (int k = 0; k < count; ++k) {
-        if (ns[k] < 1 || ns[k] > HAC_MAX_BATCH_N)
-            return fail(c, HAC_EINVAL, "instance %d: n=%d outside 1..%d", k, ns[k], HAC_MAX_BATCH_N);
-        if (linkages[k] < 0 || linkages[k] > HAC_CENTROID)
-            return fail(c, HAC_EINVAL, "instance %d: linkage %d", k, linkages[k]);
-        if (offsets[k] < 0 || out_offsets[k] < 0) return fail(c, HAC_EINVAL, "instance %d: negative offset", k);
-        extent = std::max(extent, offsets[k] + (int64_t)ns[k] * ns[k]);
-        rec_extent = std::max(rec_extent, out_offsets[k] + (int64_t)ns[k] - 1);
-    }
-    int rc = set_device(c);
+    char msg[192];
+    int rc = hac::check_batch_args(packed, offsets, ns, linkages, count, out, out_offsets, flags, &extent,
+                                   &rec_extent, msg, sizeof msg);
+    if (rc) return checked(c, rc, msg);
+    rc = set_device(c);
     if (rc) return rc;
     if (c->pending) (void)hac_sync(c);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

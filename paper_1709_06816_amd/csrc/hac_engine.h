@@ -67,6 +67,8 @@ enum : int32_t {
                        // their workgroup waits in the next exchange (single instance, g > 1)
     kFlagAfterRounds = 8,  // k_run queued behind the round engine: runs only on kHandover
     kFlagNoHandover = 16,  // round engine: never hand over, rounds to the end (HAC_OPT_ROUNDS = 2)
+    kFlagStall = 32,       // failure test: workgroup 0 never publishes, so the other
+                           // workgroups' bounded waits expire (HAC_OPT_INJECT_STALL)
 };
 
 // State left by the round engine when it hands an instance over part-way

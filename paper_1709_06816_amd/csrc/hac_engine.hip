@@ -317,7 +317,7 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
         // see barrier_stores_done) becomes visible to whoever observes the
         // slot.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        put_slot(base + (size_t)w * kSlotStride, s_acc[b][0], s_acc[b][1], gen);
+        if (!((I.flags & kFlagStall) && w == 0)) put_slot(base + (size_t)w * kSlotStride, s_acc[b][0], s_acc[b][1], gen);
     }
     if (I.exchange == kExchAllToAll || w == 0) {
         if (threadIdx.x < 64) {  // wave 0 polls: lane t reads slots t, t+64, ...

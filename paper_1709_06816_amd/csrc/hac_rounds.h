@@ -55,7 +55,9 @@ Resume rounds_resume(int n, int G, void *ws);
 
 // Records of the workspace (round engine, then any kernel it handed over
 // to) written to `out` in merge order.
-hipError_t launch_rank(int n, hac_merge *out, const uint32_t *status, void *ws, int G, hipStream_t stream);
+// Nothing is written if the launch failed (status or ctl->error set).
+hipError_t launch_rank(int n, hac_merge *out, const uint32_t *status, const Control *ctl, void *ws, int G,
+                       hipStream_t stream);
 
 // Record array of the workspace (the kernel queued behind the round engine
 // writes its records there).

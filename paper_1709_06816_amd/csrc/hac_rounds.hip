@@ -96,12 +96,13 @@ __device__ __forceinline__ bool live_at(int c) { return (s_live[c >> 5] >> (c & 
 // acquire around a monotonic arrival counter).  Returns false, the same for
 // every thread of the workgroup, if the launch was aborted or the wait
 // exceeded the watchdog (which then aborts it for all).
-__device__ bool grid_sync(RoundsCtl *rc, Control *ctl, uint32_t &gen, uint32_t G, uint64_t timeout) {
+__device__ bool grid_sync(RoundsCtl *rc, Control *ctl, uint32_t &gen, uint32_t G, uint64_t timeout,
+                          bool stall = false) {
     barrier_stores_done();
     if (threadIdx.x == 0) {
         ++gen;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(&rc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!stall) __hip_atomic_fetch_add(&rc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t target = gen * G;
         uint32_t fail = 0;
         const uint64_t t0 = wall_clock64();
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
     }
     __syncthreads();
     uint32_t gen = 0;
-    if (!grid_sync(V.rc, ctl, gen, G, timeout)) return;
+    if (!grid_sync(V.rc, ctl, gen, G, timeout, (flags & kFlagStall) && w == 0)) return;
     const int nseg = (n + kSeg - 1) / kSeg;
     // First cache entries: every row's minimum over the whole row.
     for (int t = gw; t < n * nseg; t += NW) {
@@ -542,10 +543,13 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
 // Records in merge order: record r goes to the rank of its key among all
 // m keys (keys are distinct: one survivor merges once per round).
 __global__ __launch_bounds__(256) void k_rank(const int4 *__restrict__ rec, const uint64_t *__restrict__ key, int m,
-                                              hac_merge *out, const uint32_t *status) {
+                                              hac_merge *out, const uint32_t *status, const Control *ctl) {
     constexpr int kTileKeys = 2048;
     __shared__ uint64_t tile[kTileKeys];
-    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
+    // Nothing to sort after rejected input or an abandoned launch.
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrInput | kErrTimeout | kErrInternal))
+        return;
+    if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const int r = (int)blockIdx.x * 256 + (int)threadIdx.x;
     const uint64_t mine = r < m ? key[r] : kNone;
     int rank = 0;
@@ -607,12 +611,13 @@ hipError_t launch_rounds(float *D, int n, int link, uint32_t *status, Control *c
                                       stream);
 }
 
-hipError_t launch_rank(int n, hac_merge *out, const uint32_t *status, void *ws, int G, hipStream_t stream) {
+hipError_t launch_rank(int n, hac_merge *out, const uint32_t *status, const Control *ctl, void *ws, int G,
+                       hipStream_t stream) {
     const RoundsLayout Lo = rounds_layout(n, G);
     const int m = n - 1;
     hipLaunchKernelGGL(k_rank, dim3((m + 255) / 256), dim3(256), 0, stream,
                        reinterpret_cast<const int4 *>(static_cast<char *>(ws) + Lo.rec),
-                       reinterpret_cast<const uint64_t *>(static_cast<char *>(ws) + Lo.key), m, out, status);
+                       reinterpret_cast<const uint64_t *>(static_cast<char *>(ws) + Lo.key), m, out, status, ctl);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@
 #include "hac_arena.h"
 #include "hac_ctx_info.h"
 #include "hac_engine.h"
+#include "hac_validate.h"
 
 namespace {
 
@@ -532,10 +533,11 @@ int hac_server_create(hac_ctx *ctx, size_t hbm_budget_bytes, int32_t max_jobs, i
 int hac_submit(hac_server *s, const float *host_dist, int64_t ld, int32_t n, int32_t linkage, uint64_t *ticket) {
     if (!s) return HAC_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
-    if (!host_dist || !ticket) return sfail(s, HAC_EINVAL, "NULL argument");
-    if (n < 1 || n > s->max_n) return sfail(s, HAC_EINVAL, "n=%d outside 1..%d", n, s->max_n);
-    if (ld < n) return sfail(s, HAC_EINVAL, "ld=%lld < n=%d", (long long)ld, n);
-    if (linkage < 0 || linkage > HAC_CENTROID) return sfail(s, HAC_EINVAL, "linkage %d", linkage);
+    {
+        char msg[192];
+        if (hac::check_submit_args(host_dist, ld, n, linkage, ticket, s->max_n, msg, sizeof msg) != HAC_OK)
+            return sfail(s, HAC_EINVAL, "%s", msg);
+    }
     if (s->failed != HAC_OK) return s->failed;
     if (s->quit) return sfail(s, HAC_EINVAL, "server is shutting down");
     const int g = group_for(n, s->info.lds_max);
