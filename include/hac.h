@@ -310,6 +310,8 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *                      the last ones of a run, or single linkage on input with
  *                      many equal values) and the one-merge-per-step kernel made
  *                      the remaining merges
+ *   compactions:       HAC_MODE_SCAN: times the live rows and columns were
+ *                      copied into a smaller matrix
  */
 typedef struct {
     double kernel_ms;
@@ -327,7 +329,7 @@ typedef struct {
     int32_t deferred;
     int32_t rounds;
     int32_t handed_over;
-    int32_t reserved;
+    int32_t compactions;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

@@ -73,7 +73,7 @@ class _Stats(ctypes.Structure):
                 ("phase_max_ms", ctypes.c_double * 5), ("group", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("forced_rounds", ctypes.c_int64),
                 ("deferred", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("handed_over", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("handed_over", ctypes.c_int32), ("compactions", ctypes.c_int32)]
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")
@@ -197,7 +197,7 @@ class Context:
         s = _Stats()
         self._check(self._lib.hac_get_stats(self._h, ctypes.byref(s)))
         out = {f: getattr(s, f) for f, _ in _Stats._fields_
-               if f not in ("reserved", "phase_avg_ms", "phase_max_ms")}
+               if f not in ("phase_avg_ms", "phase_max_ms")}
         out["phase_avg_ms"] = dict(zip(PHASES, list(s.phase_avg_ms)))
         out["phase_max_ms"] = dict(zip(PHASES, list(s.phase_max_ms)))
         return out

@@ -6,10 +6,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhac.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hac_engine.hip", "hac_rounds.hip", "hac_rmsd.hip", "hac_api.cpp",
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hac_engine.hip", "hac_rounds.hip", "hac_scan.hip", "hac_rmsd.hip", "hac_api.cpp",
                                                    "hac_serve.cpp", "hac_validate.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("hac_engine.h", "hac_dev.h", "hac_rounds.h", "hac_ctx_info.h",
-                                                   "hac_arena.h", "hac_rmsd.h", "hac_qcp.h", "hac_validate.h")] + [
+                                                   "hac_arena.h", "hac_rmsd.h", "hac_qcp.h", "hac_validate.h", "hac_scan.h")] + [
     os.path.join(ROOT, "include", "hac.h")]
 
 # Floating point: no contraction into FMA, no fast-math, denormals kept, and no

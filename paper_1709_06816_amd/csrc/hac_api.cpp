@@ -16,6 +16,7 @@
 #include "hac_engine.h"
 #include "hac_rmsd.h"
 #include "hac_rounds.h"
+#include "hac_scan.h"
 #include "hac_validate.h"
 
 namespace {
@@ -50,6 +51,8 @@ struct hac_ctx {
     void *scratch = nullptr;     // this device's static scratch array (hac_run_noalloc)
     float *dcopy = nullptr;      // HAC_PRESERVE_INPUT copy
     size_t dcopy_cap = 0;        // bytes
+    float *spare = nullptr;      // HAC_MODE_SCAN: the compacted matrix's second buffer
+    size_t spare_cap = 0;        // bytes
     void *rmsd_ws = nullptr;     // RMSD producer: coordinate planes, norms, status
     size_t rmsd_cap = 0;
     hac_merge *dout = nullptr;   // device merge records when the caller's out is host memory
@@ -74,6 +77,7 @@ struct hac_ctx {
     int pending_count = 0;           // status words to check
     int pending_wgs = 0, pending_block = 0, pending_group = 0, pending_graph = 0, pending_deferred = 0;
     bool pending_rounds = false;
+    bool pending_scan = false;
     int pending_seq_wgs = 0, pending_seq_block = 0, pending_seq_deferred = 0;  // kernel queued behind the rounds
 };
 
@@ -194,6 +198,7 @@ int check_status(hac_ctx *c) {
     c->stats.forced_rounds = (int64_t)ctl->forced;
     c->stats.deferred = c->pending_deferred;
     c->stats.rounds = c->pending_rounds ? (int32_t)ctl->rounds : 0;
+    c->stats.compactions = c->pending_scan ? (int32_t)ctl->rounds : 0;
     c->stats.workgroups = c->pending_wgs;
     c->stats.block = c->pending_block;
     c->stats.group = c->pending_group;
@@ -495,6 +500,7 @@ int hac_destroy(hac_ctx *c) {
     clear_graphs(c);
     if (c->ws) (void)hipFree(c->ws);
     if (c->dcopy) (void)hipFree(c->dcopy);
+    if (c->spare) (void)hipFree(c->spare);
     if (c->rmsd_ws) (void)hipFree(c->rmsd_ws);
     if (c->dout) (void)hipFree(c->dout);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -728,6 +734,67 @@ int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *o
     return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
 }
 
+// hac_run with HAC_MODE_SCAN: the scan engine over every CU.
+int run_scan(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out, uint32_t flags, hipStream_t s) {
+    if (!c->coop) return fail(c, HAC_EDEVICE, "device does not support cooperative launch");
+    if (hac::scan_lds_bytes(n) > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit in LDS", n);
+    int G = c->cus * hac::scan_occupancy(n);
+    if (c->opt_wgs > 0) G = std::min(G, (int)c->opt_wgs);
+    // Workspace: control | status | first upper row minima (set-up kernel) | scan engine.
+    const size_t ctl_bytes = align_up(sizeof(hac::Control), kAlign);
+    const size_t st_off = ctl_bytes, st_bytes = kAlign;
+    const size_t rk_off = st_off + st_bytes, rk_bytes = align_up((size_t)n * 8, kAlign);
+    const size_t sc_off = rk_off + rk_bytes;
+    const hac::ScanLayout Lo = hac::scan_layout(n, G);
+    int rc = ensure_dev(c, &c->ws, &c->ws_cap, sc_off + Lo.bytes, "workspace");
+    if (rc) return rc;
+    rc = ensure_dev(c, reinterpret_cast<void **>(&c->spare), &c->spare_cap, hac::scan_spare_floats(n) * 4,
+                    "scan buffer");
+    if (rc) return rc;
+    rc = ensure_pinned(c, ctl_bytes + kAlign);
+    if (rc) return rc;
+    char *ws = reinterpret_cast<char *>(c->ws);
+    float *D = dist;
+    if (flags & HAC_PRESERVE_INPUT) {
+        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dcopy), &c->dcopy_cap, (size_t)n * n * 4, "input copy");
+        if (rc) return rc;
+        D = c->dcopy;
+    }
+    hac_merge *dev_out = out;
+    if (!(flags & HAC_OUT_DEVICE)) {
+        size_t cap_bytes = c->dout_cap * sizeof(hac_merge);
+        rc = ensure_dev(c, reinterpret_cast<void **>(&c->dout), &cap_bytes, (size_t)(n - 1) * sizeof(hac_merge),
+                        "merge buffer");
+        if (rc) return rc;
+        c->dout_cap = cap_bytes / sizeof(hac_merge);
+        dev_out = c->dout;
+    }
+    hac::Instance inst{};
+    inst.D = D;
+    inst.out = dev_out;
+    inst.rowkey = reinterpret_cast<uint64_t *>(ws + rk_off);
+    inst.status = reinterpret_cast<uint32_t *>(ws + st_off);
+    inst.n = n;
+    inst.link = linkage;
+    hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
+    HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    HIP_TRY(c, hac::launch_zero(ws, (st_off + st_bytes) / 4, s));
+    HIP_TRY(c, hac::launch_zero(ws + sc_off + Lo.ctl, sizeof(hac::ScanCtl) / 4, s));
+    HIP_TRY(c, hac::launch_setup(inst, dist, s));
+    HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    hipError_t e = hac::launch_scan(D, c->spare, n, linkage, dev_out, inst.status, ctl, ws + sc_off, G,
+                                    timeout_ticks(c), c->opt_stall ? hac::kFlagStall : 0, s);
+    if (e != hipSuccess) return hip_fail(c, e, "scan kernel launch");
+    HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    c->pending_wgs = G;
+    c->pending_block = hac::kScanBlock;
+    c->pending_group = G;
+    c->pending_graph = 0;
+    c->pending_deferred = 0;
+    c->pending_scan = true;
+    return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
+}
+
 // hac_run and hac_run_noalloc.  noalloc: the device scratch is the static
 // array (c->scratch) instead of the context's workspace, the merge kernel
 // runs on at most HAC_NOALLOC_MAX_WORKGROUPS workgroups, out is device
@@ -744,10 +811,12 @@ int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     c->stats = hac_stats{};
     c->pending_rounds = false;
+    c->pending_scan = false;
     if (n == 1) return HAC_OK;
     if (!noalloc && !(flags & HAC_MODE_SCAN) && (linkage == HAC_SINGLE || linkage == HAC_COMPLETE) &&
         (c->opt_rounds == 2 || (c->opt_rounds == 1 && n >= kRoundsMinN)))
         return run_rounds(c, dist, n, linkage, out, flags, s);
+    if (!noalloc && (flags & HAC_MODE_SCAN)) return run_scan(c, dist, n, linkage, out, flags, s);
 
     int g = 1, block = hac::kRunBlock;
     int32_t run_flags = 0;
@@ -947,6 +1016,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->pending_graph = graphed;
     c->pending_deferred = 0;
     c->pending_rounds = false;
+    c->pending_scan = false;
     return finish(c, s, count, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)rec_extent, flags, c->ws);
 }
 

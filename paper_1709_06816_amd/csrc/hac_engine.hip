@@ -70,33 +70,6 @@ constexpr int kMaxWaves = 16;
 template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
 template <int B> constexpr int seg_unroll() { return B >= 1024 ? 4 : 8; }
 
-// Table 1 update, fp32, fixed order, no contraction.  Coefficients are fp64
-// quotients rounded once to fp32 (ai, aj, bij: the per-merge coefficients of
-// the group-average and centroid rows).  Single/complete use the exact closed
-// forms min/max of the Table 1 rows (1/2, 1/2, 0, -+1/2).
-__device__ __forceinline__ float lw_update(int link, float dki, float dkj, float dij, int ni,
-                                           int nj, int nk, float ai, float aj, float bij) {
-    float v;
-    if (link == HAC_SINGLE) {
-        v = fminf(dki, dkj);
-    } else if (link == HAC_COMPLETE) {
-        v = fmaxf(dki, dkj);
-    } else if (link == HAC_AVERAGE) {
-        v = __fadd_rn(__fmul_rn(ai, dki), __fmul_rn(aj, dkj));
-    } else if (link == HAC_WEIGHTED) {
-        v = __fadd_rn(__fmul_rn(0.5f, dki), __fmul_rn(0.5f, dkj));
-    } else if (link == HAC_CENTROID) {
-        v = __fadd_rn(__fadd_rn(__fmul_rn(ai, dki), __fmul_rn(aj, dkj)), __fmul_rn(bij, dij));
-    } else {
-        double t = (double)(ni + nj + nk);
-        float wi = (float)((double)(ni + nk) / t);
-        float wj = (float)((double)(nj + nk) / t);
-        float wb = (float)(-(double)nk / t);
-        v = __fadd_rn(__fadd_rn(__fmul_rn(wi, dki), __fmul_rn(wj, dkj)), __fmul_rn(wb, dij));
-    }
-    return v == 0.0f ? 0.0f : v;
-}
-
 // 64-bit value of the lane picked by DPP control CTRL; lanes of rows outside
 // ROW_MASK keep their own value.  All lanes must be active.
 template <int CTRL, int ROW_MASK>

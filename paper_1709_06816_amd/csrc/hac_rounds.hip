@@ -87,46 +87,13 @@ __shared__ uint32_t s_live[kMaskWords];          // live bitmask of all slots (s
 __shared__ int2 s_pair[kRoundsMaxPairs + 1];     // this round's pairs (i, j)
 __shared__ uint64_t s_red[W];
 __shared__ int s_np, s_p0;
-__shared__ uint32_t s_fail;
 
 __device__ __forceinline__ bool live_at(int c) { return (s_live[c >> 5] >> (c & 31)) & 1u; }
 
-// Grid barrier: every workgroup's writes before it are visible to every
-// workgroup after it (stores complete, then an agent-scope release and
-// acquire around a monotonic arrival counter).  Returns false, the same for
-// every thread of the workgroup, if the launch was aborted or the wait
-// exceeded the watchdog (which then aborts it for all).
-__device__ bool grid_sync(RoundsCtl *rc, Control *ctl, uint32_t &gen, uint32_t G, uint64_t timeout,
-                          bool stall = false) {
-    barrier_stores_done();
-    if (threadIdx.x == 0) {
-        ++gen;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (!stall) __hip_atomic_fetch_add(&rc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = gen * G;
-        uint32_t fail = 0;
-        const uint64_t t0 = wall_clock64();
-        for (uint32_t it = 1;; ++it) {
-            if (__hip_atomic_load(&rc->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-            if ((it & 63u) == 0) {
-                if (__hip_atomic_load(&rc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    fail = 1;
-                    break;
-                }
-                if (wall_clock64() - t0 > timeout) {
-                    atomicOr(&ctl->error, kErrTimeout);
-                    __hip_atomic_store(&rc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    fail = 1;
-                    break;
-                }
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s_fail = fail;
-    }
-    __syncthreads();
-    return s_fail == 0;
+// Grid barrier of the round engine (see hac_dev.h).
+__device__ __forceinline__ bool grid_sync(RoundsCtl *rc, Control *ctl, uint32_t &gen, uint32_t G, uint64_t timeout,
+                                          bool stall = false) {
+    return hac::grid_sync(&rc->bar, &rc->abort, &ctl->error, kErrTimeout, gen, G, timeout, stall);
 }
 
 template <class T>
