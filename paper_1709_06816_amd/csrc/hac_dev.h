@@ -67,6 +67,23 @@ __device__ __forceinline__ void barrier_stores_done() {
     __syncthreads();
 }
 
+// Release before publishing with a relaxed store or atomic (one thread, after
+// barrier_stores_done): write this XCD's L2 back, then wait for that write
+// back to finish.  The fence alone is not enough here: the compiler places
+// the wait that completes the write back (buffer_wbl2) only while the wave
+// has other memory operations outstanding, and right after
+// barrier_stores_done it has none, so the flag could leave before the data it
+// publishes has reached memory and a reader on another XCD would fetch the
+// old values.  The explicit wait restores the documented release sequence.
+__device__ __forceinline__ void release_agent() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
+}
+__device__ __forceinline__ void release_system() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
 // Wave-wide reductions from the ROCm device library (DPP lane moves, no LDS
 // round trips); the result is uniform across the wave.  Call with every lane
 // of the wave active.
@@ -91,7 +108,7 @@ __device__ inline bool grid_sync(uint32_t *bar, uint32_t *abort, uint32_t *error
     barrier_stores_done();
     if (threadIdx.x == 0) {
         ++gen;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        release_agent();
         if (!stall) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t target = gen * G;
         uint32_t fail = 0;

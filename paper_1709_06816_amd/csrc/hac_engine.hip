@@ -289,7 +289,7 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
         // Everything this workgroup wrote before the last barrier (complete,
         // see barrier_stores_done) becomes visible to whoever observes the
         // slot.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        release_agent();
         if (!((I.flags & kFlagStall) && w == 0)) put_slot(base + (size_t)w * kSlotStride, s_acc[b][0], s_acc[b][1], gen);
     }
     if (I.exchange == kExchAllToAll || w == 0) {
@@ -311,7 +311,7 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
         }
         __syncthreads();
         if (I.exchange == kExchReducer && threadIdx.x == 0 && !s_fail) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            release_agent();
             put_slot(base + (size_t)g * kSlotStride, s_acc[b][2], s_acc[b][3], gen);
         }
     } else {
@@ -989,7 +989,8 @@ __device__ bool serve_claim(ServeHost *host, const ServeEntry *ring, uint32_t ca
                 const unsigned long long hf =
                     __hip_atomic_load(&host->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_fetch_max(&dev->tail, hf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&dev->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                release_agent();
+                __hip_atomic_store(&dev->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 continue;
             }
             __builtin_amdgcn_s_sleep(8);
@@ -1004,7 +1005,8 @@ __device__ bool serve_claim(ServeHost *host, const ServeEntry *ring, uint32_t ca
         // never does, stop as if it had (entries are still taken first).
         if ((it & 255u) == 0 && wall_clock64() - t0 > idle_ticks) {
             __hip_atomic_fetch_add(&dev->self_stops, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&dev->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            release_agent();
+            __hip_atomic_store(&dev->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1090,8 +1092,8 @@ __global__ __launch_bounds__(B) void k_serve(ServeHost *host, const ServeEntry *
         barrier_stores_done();
         uint32_t *words = e.inst.status;  // [0] status, [1] members done
         if (threadIdx.x == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-            __hip_atomic_fetch_add(words + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            release_system();
+            __hip_atomic_fetch_add(words + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_inst = 1;
             if (e.rank == 0) {
                 // Member 0 wrote the merge records, so it publishes the
@@ -1127,7 +1129,7 @@ __global__ __launch_bounds__(B) void k_serve(ServeHost *host, const ServeEntry *
             if (threadIdx.x == 0) {
                 __hip_atomic_store(words, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(words + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                release_system();
                 __hip_atomic_store(done + e.job, ((unsigned long long)e.seq << 32) | s_status, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_SYSTEM);
             }

@@ -127,6 +127,44 @@ def test_server_mix_matches_run(ctx, torch, hac):
             assert not bad, bad
 
 
+def test_server_saturated_groups_match_run(ctx, torch, hac):
+    """Group jobs under saturation: 240 jobs of n in [2049, 5000] (every one
+    on a group of workgroups, so every merge exchanges minima between
+    workgroups on different XCDs), kept at the job limit for two rounds; every
+    merge list byte-identical to hac_run.  A release that lets the exchange
+    flag out before the L2 write-back of the data it publishes shows up here
+    as a few merge heights read from values one update old."""
+    N, count = 5000, 240
+    pool = [torch.empty((N, N), dtype=torch.float32).pin_memory() for _ in range(2)]
+    synth.serve_pool(2, N, seed=77, out=[p.numpy() for p in pool])
+    rng = np.random.default_rng(11)
+    ns = np.minimum(synth.log_uniform_int(rng, 2049, N, size=count), N)
+    links = rng.integers(0, 4, size=count)
+    refs = [_run_ref(ctx, torch, pool[k % 2][:int(ns[k]), :int(ns[k])].numpy(), int(links[k]))
+            for k in range(count)]
+    with hac.Server(ctx, budget_bytes=16 << 30, max_jobs=48, max_n=N) as srv:
+        for rnd in range(2):
+            _say("saturated groups round", rnd)
+            tickets, got, k = {}, {}, 0
+            t0 = time.time()
+            while len(got) < count:
+                while k < count:
+                    try:
+                        tickets[k] = srv.submit(pool[k % 2][:int(ns[k]), :int(ns[k])], int(links[k]))
+                    except hac.HacError as e:
+                        assert e.code == hac.HAC_EBUSY
+                        break
+                    k += 1
+                for q in [q for q in tickets if q not in got]:
+                    r = srv.poll(tickets[q])
+                    if r is not None:
+                        got[q] = r
+                assert time.time() - t0 < 90, "jobs not done after 90 s"
+                time.sleep(0.0005)
+            bad = [(q, int(ns[q]), int(links[q])) for q in range(count) if got[q].tobytes() != refs[q].tobytes()]
+            assert not bad, bad
+
+
 def test_server_budget_makes_jobs_wait(ctx, torch, hac):
     n, count = 1200, 24
     mats = [synth.batch_instance(n, 7300 + k) for k in range(count)]
