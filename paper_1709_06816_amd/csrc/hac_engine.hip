@@ -275,12 +275,16 @@ __device__ bool get_slot(const uint64_t *s, uint64_t gen, uint64_t &p1, uint64_t
 // the rest of the group, and leave the group-wide minima in s_acc[e&1][2..3]
 // (Section 5.3 steps 2-4: every processor ends up with the same global
 // minimum).  The caller's last barrier before the call must be
-// barrier_stores_done(), so that the release below covers every wave's
-// stores.  Ends with a barrier.  Returns false if the wait was abandoned; the
-// decision is the same for every thread.
+// barrier_stores_done(), so that every wave's stores are complete.  With
+// `writeback` the slot follows a release that writes this XCD's L2 back (the
+// caller wrote what it publishes with plain stores); without it the caller
+// wrote everything it publishes since its last exchange with agent-scope
+// stores, which are at the device's point of coherence once complete, and the
+// slot follows at once.  Ends with a barrier.  Returns false if the wait was
+// abandoned; the decision is the same for every thread.
 template <int B>
 __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Control *ctl,
-                               uint64_t timeout) {
+                               uint64_t timeout, bool writeback) {
     const int b = e & 1;
     const uint64_t gen = e & 0xFFFFu;
     uint64_t *base = I.slots + (size_t)b * (g + 1) * kSlotStride;
@@ -289,7 +293,7 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
         // Everything this workgroup wrote before the last barrier (complete,
         // see barrier_stores_done) becomes visible to whoever observes the
         // slot.
-        release_agent();
+        if (writeback) release_agent();
         if (!((I.flags & kFlagStall) && w == 0)) put_slot(base + (size_t)w * kSlotStride, s_acc[b][0], s_acc[b][1], gen);
     }
     if (I.exchange == kExchAllToAll || w == 0) {
@@ -311,7 +315,7 @@ __device__ bool group_exchange(const Instance &I, int g, int w, uint32_t e, Cont
         }
         __syncthreads();
         if (I.exchange == kExchReducer && threadIdx.x == 0 && !s_fail) {
-            release_agent();
+            if (writeback) release_agent();
             put_slot(base + (size_t)g * kSlotStride, s_acc[b][2], s_acc[b][3], gen);
         }
     } else {
@@ -524,13 +528,13 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             if (tid == 0)
                 for (int q = 0; q < 4; ++q) s_acc[b ^ 1][q] = kEmpty;
             barrier_stores_done();
-            if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+            if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout, false)) return;
         } else {
             // The candidates were folded during the last update (and are
             // published at once).  Alone, a workgroup still needs a barrier
             // here: thread 0's size update of the last merge is read below.
             if (g > 1) {
-                if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+                if (!group_exchange<B>(I, g, w, e, ctl, timeout, false)) return;
             } else {
                 __syncthreads();
             }
@@ -574,7 +578,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             fold_candidates<B>(L, n, g, w, own_ch, -1, &s_acc[b][0]);
             barrier_stores_done();
             if (g > 1) {
-                if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+                if (!group_exchange<B>(I, g, w, e, ctl, timeout, false)) return;
                 win = s_acc[b][2];
             } else {
                 win = s_acc[b][0];
@@ -680,10 +684,11 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 if (k >= n || k == i || k == j || !is_live(L.amask, k)) continue;
                 const int nk = link == HAC_WARD ? (int)L.size1[k] + 1 : 1;
                 const float v = lw_update(link, a[u], bv[u], h, ni, nj, nk, ai, aj, bij);
-                if (defer) {
-                    // Written through to the device's point of coherence, so
-                    // that the release before the next exchange has little to
-                    // write back while rescans run beside it (measured).
+                if (g > 1) {
+                    // Other workgroups read these entries after the next
+                    // exchange: agent-scope stores put them at the device's
+                    // point of coherence, so the exchange needs no L2 write
+                    // back (which would wait for every dirty line of the XCD).
                     __hip_atomic_store(reinterpret_cast<uint32_t *>(Di + k), __float_as_uint(v), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(reinterpret_cast<uint32_t *>(D + (size_t)k * n + i), __float_as_uint(v),
@@ -744,7 +749,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
             // Every workgroup's updated entries are in place (epoch e+1).
             ++e;
             b = e & 1;
-            if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+            if (g > 1 && !group_exchange<B>(I, g, w, e, ctl, timeout, false)) return;
             for (int li = tid; li < own_ch * 64; li += B) {
                 const int k = row_of_local(li, g, w);
                 L.cache[li] = kEmptyRow;
@@ -885,7 +890,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
         const uint32_t e = epoch_base + 1u;
         if (threadIdx.x == 0) s_acc[e & 1][0] = s_acc[e & 1][1] = s_acc[e & 1][2] = s_acc[e & 1][3] = kEmpty;
         barrier_stores_done();  // the mirror (and a served job's copy-in) stores are complete
-        if (!group_exchange<B>(I, g, w, e, ctl, timeout)) return;
+        if (!group_exchange<B>(I, g, w, e, ctl, timeout, true)) return;
         epoch0 = e;
         if (__hip_atomic_load(I.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrInput) return;
     } else if (okv == 0) {
