@@ -1,15 +1,25 @@
-"""Benchmark: full dendrogram of the n=32768 RMSD-like complete-linkage
-workload on one MI355X, plus the batched workload against a per-instance
-launch loop, plus the CPU oracle on a bounded sample.
+"""Benchmark of the Lance-Williams clustering library on one MI355X.
 
-Prints one JSON line.  A step is one hac_run over the whole n=32768 instance
-(set-up, all 32767 merges, merge list back in device memory) with the input
-already resident in HBM; HAC_PRESERVE_INPUT makes each step start from the
-same input (the 4 GiB device-to-device copy is inside the timed step).
+Prints one JSON line.  The headline is the n=32768 RMSD-like complete-linkage
+dendrogram (BASELINE workload 3) through the default path of hac_run (rounds
+of reciprocal-nearest-neighbour merges, the tail handed to the
+one-merge-per-step kernel); a step is one hac_run over the whole instance
+(set-up, all 32767 merges, records sorted into merge order in device memory)
+with the input already in HBM; HAC_PRESERVE_INPUT makes each step start from
+the same input (the working copy is written by the set-up kernel inside the
+step).  Beside it, on the same input: the one-merge-per-step engine and the
+paper's own full scan before every merge (HAC_MODE_SCAN), each compared byte
+for byte with the headline list; per-workload lines for the n=512 and
+n=8192 workloads (GPU and oracle times, bit-exact flags, error against an
+fp64 replay); the 1024-instance batch against a per-instance loop; serving
+under Poisson arrivals, at saturation and against a per-instance loop; the
+RMSD input producer; and the CPU oracle on bounded samples.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batch] [--no-cpu]
+                    [--no-serve] [--no-scan] [--no-rmsd] [--no-configs]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,21 +33,26 @@ if ROOT not in sys.path:
 
 METRIC = "HBM GB/s & dendrogram s at n=32768; batched instances/s vs per-instance loop"
 HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
+CSRC = os.path.join(ROOT, "paper_1709_06816_amd", "csrc")
+# Counter profiles: kernel -> (file, sources whose hash the counters were taken on).
+PROFILES = {
+    "k_rounds": ("k_rounds_rmsd_like_n32768_pmc.md", ["hac_rounds.hip", "hac_rounds.h", "hac_dev.h",
+                                                      "hac_engine.hip", "hac_engine.h"]),
+    "k_scan": ("k_scan_rmsd_like_n32768_pmc.md", ["hac_scan.hip", "hac_scan.h", "hac_dev.h"]),
+    "k_run": ("k_run_rmsd_like_n32768_pmc.md", ["hac_engine.hip", "hac_engine.h", "hac_dev.h"]),
+}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-PMC_PROFILE = os.path.join(ROOT, "profiles", "k_run_rmsd_like_n32768_pmc.md")
-ENGINE_SOURCES = [os.path.join(ROOT, "paper_1709_06816_amd", "csrc", f) for f in ("hac_engine.hip", "hac_engine.h")]
-
-
-def alg_bytes_merge_kernel(n, st):
-    """Algorithmic HBM bytes of one launch of the merge kernel k_run: each
-    Lance-Williams update of an entry reads D[i][k], D[j][k] and writes
-    D[i][k], D[k][i] (16 bytes); each rescan reads one fp32 per live entry it
-    visits; each merge writes a 16-byte record."""
+def alg_bytes_merge(n, st):
+    """Algorithmic HBM bytes of one merge-kernel run: each Lance-Williams
+    update of an entry reads D[i][k], D[j][k] and writes D[i][k], D[k][i]
+    (16 bytes); each rescanned (or, in scan mode, scanned) live entry is
+    read once (4 bytes); each merge writes a 16-byte record."""
     return 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"] + 16.0 * (n - 1)
 
 
@@ -48,39 +63,63 @@ def alg_bytes_setup(n, preserve=True):
     return (6.0 if preserve else 4.0) * n * (n - 1)
 
 
-def measured_traffic(n):
-    """HBM bytes per k_run launch from the committed counter profile, if it
-    was taken on this input size with the engine sources as they are now."""
-    import hashlib
+def measured_traffic(kernel, n):
+    """HBM bytes per launch of `kernel` from its committed counter profile,
+    if taken at this size on the sources as they are now."""
+    fname, srcs = PROFILES[kernel]
+    path = os.path.join(ROOT, "profiles", fname)
     try:
-        line = next(l for l in open(PMC_PROFILE) if l.startswith("pmc-json:"))
+        line = next(l for l in open(path) if l.startswith("pmc-json:"))
         rec = json.loads(line[len("pmc-json:"):])
     except (OSError, StopIteration, ValueError):
         return None, "no counter profile"
     h = hashlib.sha256()
-    for p in ENGINE_SOURCES:
-        with open(p, "rb") as fh:
+    for f in srcs:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     if rec.get("engine_sha256") != h.hexdigest():
-        return None, "engine changed since the counters were taken"
+        return None, "sources changed since the counters were taken"
     if "n=%d" % n not in rec.get("workload", ""):
         return None, "counters were taken at another size"
-    return rec["traffic_bytes"], os.path.relpath(PMC_PROFILE, ROOT)
+    return rec["traffic_bytes"], os.path.relpath(path, ROOT)
 
 
-def cpu_baseline(d, link, n, budget_s, gpu_prefix):
+def golden(key):
+    try:
+        with open(GOLDEN) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def records_sha(rec_bytes):
+    return hashlib.sha256(rec_bytes).hexdigest()
+
+
+def roofline(achieved_bytes, ms, traffic, traffic_src, kernel, extra=None):
+    gbs = achieved_bytes / (ms / 1000.0) / 1e9
+    r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+         "traffic": traffic, "traffic_source": traffic_src, "kernel": kernel, "kernel_ms": ms,
+         "alg_bytes_per_launch": achieved_bytes,
+         "traffic_gbs": None if traffic is None else traffic / (ms / 1000.0) / 1e9}
+    if extra:
+        r.update(extra)
+    return r
+
+
+def cpu_baseline(d, link, n, budget_s, gpu_list, gold):
     """Time the oracle (unchanged) on the first K merges of the same input,
     K grown until the sample takes a few seconds of the budget, and
     extrapolate to the whole dendrogram by the number of cells its scan
-    visits: merge s scans m(m-1)/2 cells with m = n - s live clusters."""
+    visits: merge s scans m(m-1)/2 cells with m = n - s live clusters.  The
+    GPU list is compared with the oracle's sample and, when the stored digest
+    of the oracle's full list is present, with all of it."""
     import oracle
     threads = oracle.default_threads()
     t0 = time.perf_counter()
     oracle.run_f32(d, link, max_merges=0, threads=threads)
     t_setup = time.perf_counter() - t0
     k = 4
-    t_k = None
-    res = None
     while True:
         t0 = time.perf_counter()
         res = oracle.run_f32(d, link, max_merges=k, threads=threads)
@@ -94,18 +133,111 @@ def cpu_baseline(d, link, n, budget_s, gpu_prefix):
     cells_k = float(np.sum(ms * (ms - 1) / 2))
     per_cell = max(t_k - t_setup, 1e-9) / cells_k
     t_full = t_setup + per_cell * cells_all
-    prefix_ok = bool(res.tobytes() == gpu_prefix[:len(res)].tobytes())
-    return {
+    out = {
         "value": 1.0 / t_full, "unit": "dendrograms/s", "cores": threads, "kind": "oracle",
         "sample": "first %d of %d merges of the same n=%d input (%.1f s incl. %.1f s set-up); "
                   "whole dendrogram extrapolated by scanned cells: %.0f s" % (k, n - 1, n, t_k, t_setup, t_full),
         "est_dendrogram_s": t_full,
-        "parity_prefix_merges": int(len(res)),
-        "parity_prefix_ok": prefix_ok,
+        "sample_merges_identical": bool(res.tobytes() == gpu_list[:len(res)].tobytes()),
     }
+    if gold is not None:
+        out["full_list_identical_to_oracle"] = records_sha(gpu_list.tobytes()) == gold["records_sha256"]
+        out["oracle_full_run_s"] = gold["oracle_seconds"]
+        out["oracle_full_run_threads"] = gold["oracle_threads"]
+        out["oracle_full_run_note"] = "measured when the stored digest was written (tests/golden/make_digests.py)"
+    return out
 
 
-def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
+def run_timed(ctx, src, link, steps, out, **kw):
+    """`steps` hac_run calls; returns (median kernel_ms, median init_ms, wall ms per step, stats)."""
+    kms, ims = [], []
+    st = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run(src, link, preserve=True, out=out, **kw)
+        ctx.sync()
+        st = ctx.stats()
+        kms.append(st["kernel_ms"])
+        ims.append(st["init_ms"])
+    wall = (time.perf_counter() - t0) * 1000.0 / steps
+    return float(np.median(kms)), float(np.median(ims)), wall, st
+
+
+def engines_leg(torch, hac, ctx, src, n, link, headline_rec, scan):
+    """The other engines on the headline input: one merge per step (64
+    workgroups, deferred rescans) and the paper's full scan before every
+    merge, each with its bytes and time; lists compared with the headline's."""
+    res = {}
+    out = torch.empty((n - 1) * 16, dtype=torch.uint8, device="cuda")
+    ctx.set_option(hac.OPT_ROUNDS, 0)
+    try:
+        log("one-merge-per-step engine")
+        run_timed(ctx, src, link, 1, out)
+        kms, ims, wall, st = run_timed(ctx, src, link, 3, out)
+    finally:
+        ctx.set_option(hac.OPT_ROUNDS, 1)
+    ab = alg_bytes_merge(n, st)
+    traffic, tsrc = measured_traffic("k_run", n)
+    res["one_merge_per_step"] = {
+        "kernel": "k_run (%d workgroups, deferred rescans)" % st["workgroups"], "dendrogram_ms": wall,
+        "kernel_ms": kms, "alg_bytes": ab,
+        "roofline": roofline(ab, kms, traffic, tsrc, "k_run"),
+        "forced_rounds": st["forced_rounds"],
+        "identical_to_headline": out.cpu().numpy().tobytes() == headline_rec}
+    if scan:
+        log("paper scan mode (Section 5.3 step 1) at n=%d" % n)
+        kms, ims, wall, st = run_timed(ctx, src, link, 1, out, scan=True)
+        ab = alg_bytes_merge(n, st)
+        traffic, tsrc = measured_traffic("k_scan", n)
+        res["paper_scan_mode"] = {
+            "kernel": "k_scan (%d workgroups)" % st["workgroups"], "dendrogram_ms": wall, "kernel_ms": kms,
+            "compactions": st["compactions"], "scanned_live_entries": st["rescan_elems"],
+            "roofline": roofline(ab, kms, traffic, tsrc, "k_scan",
+                                 {"note": "the whole live upper triangle read before every merge; 4 B per "
+                                          "live entry scanned + 16 B per updated entry + 16 B per record"}),
+            "identical_to_headline": out.cpu().numpy().tobytes() == headline_rec}
+    del out
+    return res
+
+
+def config_lines(torch, hac, ctx, cpu):
+    """Workloads 1 and 2: GPU time (default path), the oracle's time on this
+    host, bit-exactness, and the largest relative height error against an
+    fp64 replay of the same merge list."""
+    import oracle
+    import synth
+    lines = []
+    jobs = [("mixture n=512 (8 isotropic Gaussians in R^8)", synth.mixture_512(), ["complete"], synth.BASE_SEED + 1),
+            ("mixture n=8192 (32 Gaussians in R^16)", synth.mixture_8192(), ["single", "complete", "average", "ward"],
+             synth.BASE_SEED + 2)]
+    threads = oracle.default_threads()
+    for name, d, links, seed in jobs:
+        n = d.shape[0]
+        src = torch.from_numpy(d).cuda()
+        out = torch.empty((n - 1) * 16, dtype=torch.uint8, device="cuda")
+        for link in links:
+            log("workload %s %s" % (name, link))
+            run_timed(ctx, src, link, 1, out)
+            kms, ims, wall, st = run_timed(ctx, src, link, 5, out)
+            got = np.frombuffer(out.cpu().numpy().tobytes(), dtype=hac.MERGE_DTYPE)
+            line = {"workload": name, "n": n, "linkage": link, "seed": seed, "gpu_ms": wall, "kernel_ms": kms,
+                    "setup_ms": ims, "engine": "rounds" if st["rounds"] else "one merge per step",
+                    "rounds": st["rounds"], "handed_over": bool(st["handed_over"])}
+            if cpu:
+                t0 = time.perf_counter()
+                exp = oracle.run_f32(d, link, threads=threads)
+                t_or = time.perf_counter() - t0
+                h64, _ = oracle.replay_f64(d, link, got, threads=threads)
+                err = np.abs(got["h"].astype(np.float64) - h64) / np.maximum(np.abs(h64), 1e-300)
+                line.update({"oracle_s": t_or, "oracle_cores": threads, "speedup": t_or * 1000.0 / wall,
+                             "bit_exact": got.tobytes() == exp.tobytes(),
+                             "max_rel_err_vs_fp64": float(err.max()) if len(err) else 0.0})
+            lines.append(line)
+        del src, out
+    return lines
+
+
+def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps, cpu):
     import synth
     spec = synth.batch_spec(count=count, n_lo=n_lo, n_hi=n_hi)
     offs, total = synth.pack_offsets(spec.ns)
@@ -114,12 +246,10 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
     for k, (n, s) in enumerate(zip(spec.ns, spec.seeds)):
         host[offs[k]:offs[k] + int(n) * int(n)] = synth.batch_instance(int(n), int(s)).ravel()
     src = torch.from_numpy(host).cuda()
-    del host
     work = torch.empty_like(src)
     moff, mtot = synth.merge_offsets(spec.ns)
     out_b = torch.empty(mtot * 16, dtype=torch.uint8, device="cuda")
     out_l = torch.empty(mtot * 16, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
 
     def one_batch():
         work.copy_(src)
@@ -132,14 +262,12 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
         obase = out_l.data_ptr()
         for k in range(count):
             n = int(spec.ns[k])
-            ctx.run_ptr(base + 4 * int(offs[k]), n, int(spec.linkages[k]),
-                        out=obase + 16 * int(moff[k]))
+            ctx.run_ptr(base + 4 * int(offs[k]), n, int(spec.linkages[k]), out=obase + 16 * int(moff[k]))
         ctx.sync()
 
     one_batch()
     torch.cuda.synchronize()
-    tb = []
-    kb = []
+    tb, kb = [], []
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -148,9 +276,6 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
         tb.append(time.perf_counter() - t0)
         kb.append(ctx.stats()["kernel_ms"])
     st = ctx.stats()
-    # Algorithmic bytes of the batch kernel: every instance's set-up (read its
-    # strict upper triangle, write the mirror) plus its merge loops, counted
-    # as for the single-instance kernel.
     ns64 = spec.ns.astype(np.float64)
     alg = float(np.sum(4.0 * ns64 * (ns64 - 1.0))) + 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"] \
         + 16.0 * float(mtot)
@@ -161,86 +286,94 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps):
     one_loop()
     torch.cuda.synchronize()
     tl = time.perf_counter() - t0
-    same = bool(torch.equal(out_b, out_l))
+    rec = out_b.cpu().numpy().tobytes()
+    same = rec == out_l.cpu().numpy().tobytes()
     tbm = float(np.median(tb))
-    return {
+    kbm = float(np.median(kb))
+    res = {
         "workload": "%d instances, n log-uniform in [%d, %d], linkage uniform over 4, "
                     "Gaussian mixtures in R^16, packed ragged (%.2f GB)" % (count, n_lo, n_hi, total * 4 / 1e9),
-        "instances_per_s": count / tbm,
-        "batch_s": tbm,
-        "batch_kernel_ms": float(np.median(kb)),
-        "loop_instances_per_s": count / tl,
-        "loop_s": tl,
-        "speedup_vs_loop": tl / tbm,
-        "identical_to_loop": same,
-        "merges": int(mtot),
-        "alg_bytes": alg,
-        "achieved_gbs": alg / (float(np.median(kb)) / 1000.0) / 1e9,
-        "frac_hbm_peak": alg / (float(np.median(kb)) / 1000.0) / 1e9 / HBM_PEAK_GBS,
-        "plan": {"block": st["block"], "group": st["group"], "workgroups": st["workgroups"],
-                 "graph": st["graph"]},
+        "instances_per_s": count / tbm, "batch_s": tbm, "batch_kernel_ms": kbm,
+        "loop_instances_per_s": count / tl, "loop_s": tl, "speedup_vs_loop": tl / tbm,
+        "identical_to_loop": same, "merges": int(mtot), "alg_bytes": alg,
+        "achieved_gbs": alg / (kbm / 1000.0) / 1e9, "frac_hbm_peak": alg / (kbm / 1000.0) / 1e9 / HBM_PEAK_GBS,
+        "plan": {"block": st["block"], "group": st["group"], "workgroups": st["workgroups"], "graph": st["graph"]},
     }
+    gold = golden("batch_1024")
+    if gold is not None and count == gold["count"]:
+        bad = [k for k, n in enumerate(spec.ns)
+               if records_sha(rec[16 * int(moff[k]):16 * (int(moff[k]) + int(n) - 1)]) != gold["records_sha256"][k]]
+        res["instances_identical_to_oracle"] = count - len(bad)
+        res["oracle_full_batch_s"] = gold["oracle_seconds"]
+        res["oracle_full_batch_threads"] = gold["oracle_threads"]
+    if cpu:
+        # The oracle, one instance per thread, on a bounded sample of the
+        # instances; extrapolated to the batch by its scanned cells.
+        import concurrent.futures as cf
+        import oracle
+        rng = np.random.default_rng(3)
+        pick = rng.choice(count, size=min(48, count), replace=False)
+        threads = oracle.default_threads()
+
+        def one(k):
+            n = int(spec.ns[k])
+            return oracle.run_f32(host[offs[k]:offs[k] + n * n].reshape(n, n), int(spec.linkages[k]), threads=1)
+
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, pick))
+        t_s = time.perf_counter() - t0
+        cells = ns64 ** 3 / 6.0
+        res["cpu_baseline"] = {"value": len(pick) / t_s * float(cells[pick].sum() / len(pick)) / float(cells.mean()),
+                               "unit": "instances/s", "cores": threads, "kind": "oracle",
+                               "sample": "%d random instances of the batch, one per thread (%.1f s), scaled to the "
+                                         "batch's mix by n^3/6 scanned cells" % (len(pick), t_s)}
+    del src, work, out_b, out_l, host
+    torch.cuda.empty_cache()
+    return res
 
 
-def scan_leg(torch, hac, ctx, n):
-    """The paper's own step (Section 5.3 step 1): every merge rescans the live
-    upper triangle instead of keeping row minima.  Same merge list as the
-    cached path; reported beside it as the memory-bound reference."""
-    import synth
-    d = synth.mixture_8192(n=n)
-    src = torch.from_numpy(d).cuda()
-    out = {}
-    for mode in ("cached", "scan"):
-        ctx.run(src, "complete", preserve=True, scan=(mode == "scan"))
-        st = ctx.stats()
-        merges = ctx.run(src, "complete", preserve=True, scan=(mode == "scan"))
-        st = ctx.stats()
-        ab = alg_bytes_merge_kernel(n, st)
-        out[mode] = {"kernel_ms": st["kernel_ms"], "alg_bytes": ab,
-                     "achieved_gbs": ab / (st["kernel_ms"] / 1000.0) / 1e9,
-                     "frac_hbm_peak": ab / (st["kernel_ms"] / 1000.0) / 1e9 / HBM_PEAK_GBS,
-                     "scanned_elems": st["rescan_elems"], "records": merges}
-    same = out["cached"].pop("records").tobytes() == out["scan"].pop("records").tobytes()
-    return {"workload": "mixture n=%d (32 Gaussians in R^16), complete linkage" % n, "n": n,
-            "identical_merge_lists": bool(same), **out,
-            "note": "scan: every workgroup reads the live upper part of its rows before every merge"}
-
-
-def serve_leg(torch, hac, ctx, requests, warmup, rate, budget_gb, big_n):
+def serve_leg(torch, hac, ctx, requests, warmup, rate, budget_gb, big_n, loop_jobs):
     """Continuous batching: Poisson arrivals submitted open-loop from host
-    page-locked memory, latency = result on the host - scheduled arrival."""
+    page-locked memory, latency = result on the host - scheduled arrival;
+    then every request at once (saturation); then the same jobs through a
+    per-instance hac_run loop (copy in, run, records back) with the same
+    arrival times.  Requests cut the top-left n x n block of one of 16
+    independent Gaussian mixtures of 16384 points each (block = the distance
+    matrix of the mixture's first n points)."""
     import synth
-    n_hi = 16384
-    pool_n = 2
-    log("serve: generating %d pool matrices of n=%d" % (pool_n, n_hi))
+    n_hi, pool_n = 16384, 16
+    log("serve: generating %d mixtures of n=%d" % (pool_n, n_hi))
     pool = [torch.empty((n_hi, n_hi), dtype=torch.float32).pin_memory() for _ in range(pool_n)]
     synth.serve_pool(pool_n, n_hi, out=[p.numpy() for p in pool])
-    big = None
-    if big_n:
-        log("serve: generating the n=%d instance" % big_n)
-        big = torch.empty((big_n, big_n), dtype=torch.float32).pin_memory()
-        synth.mixture_65536(n=big_n, out=big.numpy())
     tr = synth.serve_trace(warmup + requests, rate=rate, n_hi=n_hi)
-    srv = hac.Server(ctx, budget_bytes=int(budget_gb * (1 << 30)), max_jobs=1024,
-                     max_n=max(n_hi, big_n or 0))
+    srv = hac.Server(ctx, budget_bytes=int(budget_gb * 1e9), max_jobs=1024, max_n=max(n_hi, big_n or 0))
     res = {}
+
+    def job(k):
+        n = int(tr.ns[k])
+        return pool[k % pool_n][:n, :n], int(tr.linkages[k])
+
+    def wait(tk):
+        while True:
+            r = srv.poll(tk)
+            if r is not None:
+                return r
+            time.sleep(0.0002)
+
     try:
-        big_alone = None
-        if big is not None:
+        big = None
+        if big_n:
+            log("serve: generating the n=%d instance" % big_n)
+            big = torch.empty((big_n, big_n), dtype=torch.float32).pin_memory()
+            synth.mixture_65536(n=big_n, out=big.numpy())
             log("serve: n=%d alone" % big_n)
             t0 = time.perf_counter()
-            tk = srv.submit(big, "average")
-            while True:
-                r = srv.poll(tk)
-                if r is not None:
-                    break
-                time.sleep(0.0005)
-            big_alone = (time.perf_counter() - t0, r)
+            big_alone = (None, wait(srv.submit(big, "average")))
+            big_alone = (time.perf_counter() - t0, big_alone[1])
         big_at = warmup + requests // 4
         log("serve: %d requests at %.0f/s (+%d warm-up)" % (requests, rate, warmup))
-        pending = {}
-        done_t = {}
-        results = {}
+        pending, done_t, results = {}, {}, {}
         big_mix = None
         t_start = time.perf_counter() + 0.05
 
@@ -258,10 +391,10 @@ def serve_leg(torch, hac, ctx, requests, warmup, rate, budget_gb, big_n):
                 poll_all()
                 if due - time.perf_counter() > 0.002:
                     time.sleep(0.0005)
-            n = int(tr.ns[k])
+            m, link = job(k)
             while True:
                 try:
-                    pending[k] = srv.submit(pool[k % pool_n][:n, :n], int(tr.linkages[k]))
+                    pending[k] = srv.submit(m, link)
                     break
                 except hac.HacError as e:
                     if e.code != hac.HAC_EBUSY:
@@ -284,40 +417,85 @@ def serve_leg(torch, hac, ctx, requests, warmup, rate, budget_gb, big_n):
         lat = np.array([done_t[k] - (t_start + float(tr.arrivals[k])) for k in meas]) * 1000.0
         span = max(done_t[k] for k in meas) - (t_start + float(tr.arrivals[warmup]))
         mbytes = float(sum(4.0 * int(tr.ns[k]) ** 2 for k in meas))
-        # Alone vs in the mix: a sample of requests again, one at a time.
-        rng = np.random.default_rng(7)
-        sample = sorted(rng.choice(np.arange(warmup, len(tr.ns)), size=min(48, requests), replace=False))
-        same = True
-        for k in sample:
-            n = int(tr.ns[k])
-            tk = srv.submit(pool[k % pool_n][:n, :n], int(tr.linkages[k]))
+
+        log("serve: saturation (all %d requests at once)" % requests)
+        sat_pending, sat_res = {}, {}
+        t0 = time.perf_counter()
+        for k in meas:
+            m, link = job(k)
             while True:
-                r = srv.poll(tk)
-                if r is not None:
+                try:
+                    sat_pending[k] = srv.submit(m, link)
                     break
-                time.sleep(0.0002)
-            same &= r.tobytes() == results[k].tobytes()
+                except hac.HacError as e:
+                    if e.code != hac.HAC_EBUSY:
+                        raise
+                    for q in list(sat_pending):
+                        r = srv.poll(sat_pending[q])
+                        if r is not None:
+                            sat_res[q] = r
+                            del sat_pending[q]
+        while sat_pending:
+            for q in list(sat_pending):
+                r = srv.poll(sat_pending[q])
+                if r is not None:
+                    sat_res[q] = r
+                    del sat_pending[q]
+            time.sleep(0.0002)
+        t_sat = time.perf_counter() - t0
+        same = all(sat_res[k].tobytes() == results[k].tobytes() for k in meas)
         st = srv.stats()
-        res = {
-            "workload": "Poisson arrivals at %.0f/s, n log-uniform on [256, %d], linkage uniform over 4, "
-                        "Gaussian mixtures in R^16 (top-left blocks of %d page-locked %d-point mixtures), "
-                        "HBM budget %.0f GB" % (rate, n_hi, pool_n, n_hi, budget_gb),
-            "requests": requests, "warmup": warmup,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
-            "jobs_per_s": requests / span, "nominal_rate_per_s": rate,
-            "offered_jobs_per_s": (requests - 1) / float(tr.arrivals[len(tr.ns) - 1] - tr.arrivals[warmup]),
-            "matrix_gb_per_s": mbytes / span / 1e9,
-            "alone_vs_mix_identical": bool(same), "alone_vs_mix_sample": len(sample),
-            "peak_gb": st["peak_bytes"] / 1e9, "kernel_launches": st["kernel_launches"],
-            "workgroups": st["workgroups"], "block": st["block"],
-        }
-        if big is not None:
-            res["big"] = {"n": big_n, "linkage": "average",
-                          "alone_s": big_alone[0], "in_mix_latency_s": big_mix[2][0],
-                          "identical": bool(big_alone[1].tobytes() == big_mix[2][1].tobytes())}
     finally:
         srv.close()
+
+    # The same jobs, one hac_run after another on one stream, arriving at the
+    # same (relative) times: a job starts when it has arrived and the
+    # previous one is done.
+    log("serve: per-instance hac_run loop over %d of the requests" % loop_jobs)
+    lk = list(range(warmup, warmup + loop_jobs))
+    dev = torch.empty((n_hi, n_hi), dtype=torch.float32, device="cuda")
+    loop_lat, same_loop = [], True
+    t0 = time.perf_counter() + 0.05
+    base = float(tr.arrivals[lk[0]])
+    for k in lk:
+        due = t0 + float(tr.arrivals[k]) - base
+        while time.perf_counter() < due:
+            time.sleep(0.0002)
+        m, link = job(k)
+        n = m.shape[0]
+        d = dev.view(-1)[:n * n].view(n, n)
+        d.copy_(m, non_blocking=True)
+        r = ctx.run(d, link)
+        loop_lat.append((time.perf_counter() - due) * 1000.0)
+        same_loop &= r.tobytes() == results[k].tobytes()
+    t_loop = time.perf_counter() - t0 - 0.05
+    del dev
+    torch.cuda.empty_cache()
+    res = {
+        "workload": "Poisson arrivals at %.0f/s, n log-uniform on [256, %d], linkage uniform over 4, "
+                    "top-left blocks of %d independent Gaussian mixtures in R^16 (K ~ U{2..32}, sigma ~ "
+                    "U[0.5, 2]) in page-locked memory, HBM budget %.0f GB" % (rate, n_hi, pool_n, budget_gb),
+        "requests": requests, "warmup": warmup,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+        "jobs_per_s": requests / span, "nominal_rate_per_s": rate,
+        "offered_jobs_per_s": (requests - 1) / float(tr.arrivals[len(tr.ns) - 1] - tr.arrivals[warmup]),
+        "matrix_gb_per_s": mbytes / span / 1e9,
+        "saturation_jobs_per_s": requests / t_sat, "saturation_s": t_sat,
+        "saturation_identical_to_poisson_run": bool(same),
+        "peak_gb": st["peak_bytes"] / 1e9, "kernel_launches": st["kernel_launches"],
+        "workgroups": st["workgroups"], "block": st["block"],
+        "per_instance_loop": {"jobs": loop_jobs, "p50_ms": float(np.percentile(loop_lat, 50)),
+                              "p99_ms": float(np.percentile(loop_lat, 99)), "jobs_per_s": loop_jobs / t_loop,
+                              "identical_to_served": bool(same_loop),
+                              "note": "hac_run per job (host-to-device copy, run, records back) with the same "
+                                      "relative arrival times"},
+    }
+    if big is not None:
+        res["big"] = {"n": big_n, "linkage": "average", "alone_s": big_alone[0], "in_mix_latency_s": big_mix[2][0],
+                      "identical": bool(big_alone[1].tobytes() == big_mix[2][1].tobytes())}
+        del big
+    del pool
     return res
 
 
@@ -374,6 +552,8 @@ def rmsd_cpu_baseline(n, atoms, pairs):
             "sample": "%d random pairs of the same %d conformations (%.1f s)" % (pairs, n, dt)}
 
 
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,10 +564,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-scan", action="store_true")
-    ap.add_argument("--scan-n", type=int, default=8192)
+    ap.add_argument("--no-engines", action="store_true", help="skip the other engines on the headline input")
+    ap.add_argument("--no-configs", action="store_true", help="skip the n=512 and n=8192 workload lines")
     ap.add_argument("--no-rmsd", action="store_true")
     ap.add_argument("--rmsd-n", type=int, default=32768)
     ap.add_argument("--rmsd-atoms", type=int, default=128)
@@ -396,6 +576,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-big-n", type=int, default=65536, help="0: no big instance")
+    ap.add_argument("--serve-loop-jobs", type=int, default=400)
+    ap.add_argument("--only-scan", action="store_true", help="headline input through scan mode only (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a reference kernel of known "
                          "traffic for the HBM byte counters)")
@@ -422,23 +604,26 @@ def main():
     d = synth.rmsd_like(seed=seed, n=n)
     src = torch.from_numpy(d).cuda()
     ctx = hac.Context(0)
-    if args.workgroups:
-        ctx.set_option(hac.OPT_WORKGROUPS, args.workgroups)
     out = torch.empty((n - 1) * 16, dtype=torch.uint8, device="cuda")
-
-    def step():
-        ctx.run(src, link, preserve=True, out=out)
+    if args.only_scan:
+        kms, ims, wall, st = run_timed(ctx, src, link, 1, out, scan=True)
+        print(json.dumps({"only_scan": True, "n": n, "kernel_ms": kms, "dendrogram_ms": wall,
+                          "alg_bytes": alg_bytes_merge(n, st), "compactions": st["compactions"],
+                          "scanned_live_entries": st["rescan_elems"], "update_elems": st["update_elems"]}),
+              flush=True)
+        ctx.close()
+        return
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
-        step()
+        ctx.run(src, link, preserve=True, out=out)
         ctx.sync()
     torch.cuda.synchronize()
-    kms, ims, stats = [], [], None
     log("timing %d steps" % args.steps)
+    kms, ims, stats = [], [], None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        ctx.run(src, link, preserve=True, out=out)
         ctx.sync()
         stats = ctx.stats()
         kms.append(stats["kernel_ms"])
@@ -446,13 +631,14 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = elapsed * 1000.0 / args.steps
-    merges = np.frombuffer(out.cpu().numpy().tobytes(), dtype=hac.MERGE_DTYPE)
+    rec = out.cpu().numpy().tobytes()
+    merges = np.frombuffer(rec, dtype=hac.MERGE_DTYPE)
     kernel_ms = float(np.mean(kms))
-    ab = alg_bytes_merge_kernel(n, stats)
-    achieved = ab / (kernel_ms / 1000.0) / 1e9
-    traffic, traffic_src = measured_traffic(n)
     init_ms = float(np.mean(ims))
-    log("step %.1f ms, merge kernel %.1f ms, %d workgroups" % (ms_step, kernel_ms, stats["workgroups"]))
+    ab = alg_bytes_merge(n, stats)
+    traffic, traffic_src = measured_traffic("k_rounds", n)
+    gold = golden("rmsd_like_n32768_complete") if n == 32768 else None
+    log("step %.1f ms, merge kernels %.1f ms, %d rounds" % (ms_step, kernel_ms, stats["rounds"]))
 
     result = {
         "metric": METRIC,
@@ -467,50 +653,45 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "rmsd_like n=%d complete linkage (R^30, 64 anisotropic clusters, "
-                               "distances scaled to [0,20] and rounded to 1e-3)" % n,
+        "config": {"workload": "rmsd_like n=%d complete linkage (R^30, 64 anisotropic clusters, distances scaled "
+                               "to [0,20] and rounded to 1e-3)" % n,
                    "n": n, "linkage": link, "seed": seed, "parallelism": "1 GPU"},
         "dendrogram_s": ms_step / 1000.0,
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "traffic_source": traffic_src,
-            "kernel": "k_run (persistent merge kernel)", "kernel_ms": kernel_ms,
-            "alg_bytes_per_launch": ab, "workgroups": stats["workgroups"],
-            "rescans": stats["rescans"], "rescan_elems": stats["rescan_elems"],
-            "update_elems": stats["update_elems"],
-            "deferred_rescans": bool(stats["deferred"]), "forced_rounds": stats["forced_rounds"],
-            "merge_rounds": stats["rounds"],
-            "traffic_gbs": None if traffic is None else traffic / (kernel_ms / 1000.0) / 1e9,
-            "note": "latency-bound: one grid-wide exchange per merge; rescans run during the exchange wait",
-            "setup_kernel": {"kernel": "k_setup", "ms": init_ms, "alg_bytes": alg_bytes_setup(n),
-                             "achieved_gbs": alg_bytes_setup(n) / (init_ms / 1000.0) / 1e9
-                             if init_ms > 0 else None},
-        },
+        "full_list_identical_to_oracle": None if gold is None else records_sha(rec) == gold["records_sha256"],
+        "roofline": roofline(ab, kernel_ms, traffic, traffic_src,
+                             "k_rounds (rounds of reciprocal-nearest-neighbour merges; the tail's k_run and the "
+                             "record sort are inside the timed interval)",
+                             {"workgroups": stats["workgroups"], "rounds": stats["rounds"],
+                              "handed_over": bool(stats["handed_over"]), "rescans": stats["rescans"],
+                              "rescan_elems": stats["rescan_elems"], "update_elems": stats["update_elems"],
+                              "setup_kernel": {"kernel": "k_setup", "ms": init_ms, "alg_bytes": alg_bytes_setup(n),
+                                               "achieved_gbs": alg_bytes_setup(n) / (init_ms / 1000.0) / 1e9
+                                               if init_ms > 0 else None}}),
     }
-    if not args.no_scan:
-        log("paper scan mode at n=%d" % args.scan_n)
-        result["paper_scan_mode"] = scan_leg(torch, hac, ctx, args.scan_n)
+    if not args.no_engines:
+        result["engines"] = engines_leg(torch, hac, ctx, src, n, link, rec, not args.no_scan)
+    del src
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        result["workloads"] = config_lines(torch, hac, ctx, not args.no_cpu)
     if not args.no_rmsd:
         log("input producer: rmsd n=%d atoms=%d" % (args.rmsd_n, args.rmsd_atoms))
         result["input_producer"] = rmsd_leg(torch, hac, ctx, args.rmsd_n, args.rmsd_atoms, reps=5)
-        log("rmsd %.2f ms" % result["input_producer"]["ms"])
     if not args.no_batch:
         log("batch leg")
-        result["batched"] = batch_leg(torch, hac, ctx, args.batch_count, 64, 4096, reps=3)
+        result["batched"] = batch_leg(torch, hac, ctx, args.batch_count, 64, 4096, 3, not args.no_cpu)
     if not args.no_serve:
-        del src
-        torch.cuda.empty_cache()
         log("serving leg")
-        result["serving"] = serve_leg(torch, hac, ctx, args.serve_requests, args.serve_warmup,
-                                      args.serve_rate, args.serve_budget_gb, args.serve_big_n)
+        result["serving"] = serve_leg(torch, hac, ctx, args.serve_requests, args.serve_warmup, args.serve_rate,
+                                      args.serve_budget_gb, args.serve_big_n, args.serve_loop_jobs)
     if not args.no_cpu and "input_producer" in result:
         log("cpu baseline of the input producer")
         result["input_producer"]["cpu_baseline"] = rmsd_cpu_baseline(args.rmsd_n, args.rmsd_atoms, 200000)
     if not args.no_cpu:
         log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(d, link, n, args.cpu_budget, merges)
+        result["cpu_baseline"] = cpu_baseline(d, link, n, args.cpu_budget, merges, gold)
     ctx.close()
+    torch.cuda.synchronize()
     print(json.dumps(result), flush=True)
 
 
