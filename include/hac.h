@@ -312,6 +312,12 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *                      the remaining merges
  *   compactions:       HAC_MODE_SCAN: times the live rows and columns were
  *                      copied into a smaller matrix
+ *   rounds_ms:         hac_run through rounds of merges: device time of the
+ *                      round engine's kernel alone (kernel_ms also covers the
+ *                      kernel that takes over from it and the record sort);
+ *                      0 otherwise
+ *   rounds_rescan_elems, rounds_update_elems: that kernel's share of
+ *                      rescan_elems and update_elems
  */
 typedef struct {
     double kernel_ms;
@@ -330,6 +336,9 @@ typedef struct {
     int32_t rounds;
     int32_t handed_over;
     int32_t compactions;
+    double rounds_ms;
+    int64_t rounds_rescan_elems;
+    int64_t rounds_update_elems;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

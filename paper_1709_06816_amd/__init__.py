@@ -73,7 +73,9 @@ class _Stats(ctypes.Structure):
                 ("phase_max_ms", ctypes.c_double * 5), ("group", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("forced_rounds", ctypes.c_int64),
                 ("deferred", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("handed_over", ctypes.c_int32), ("compactions", ctypes.c_int32)]
+                ("handed_over", ctypes.c_int32), ("compactions", ctypes.c_int32),
+                ("rounds_ms", ctypes.c_double), ("rounds_rescan_elems", ctypes.c_int64),
+                ("rounds_update_elems", ctypes.c_int64)]
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")

@@ -59,7 +59,7 @@ struct hac_ctx {
     size_t dout_cap = 0;         // records
     void *pinned = nullptr;      // host staging (status read-back, descriptor upload)
     size_t pinned_cap = 0;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // [3]: end of the round engine's kernel
 
     hac_stats stats{};
     int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0, opt_exchange = 0, opt_profile = 0;
@@ -199,6 +199,15 @@ int check_status(hac_ctx *c) {
     c->stats.deferred = c->pending_deferred;
     c->stats.rounds = c->pending_rounds ? (int32_t)ctl->rounds : 0;
     c->stats.compactions = c->pending_scan ? (int32_t)ctl->rounds : 0;
+    c->stats.rounds_ms = 0.0;
+    c->stats.rounds_rescan_elems = c->stats.rounds_update_elems = 0;
+    if (c->pending_rounds) {
+        float rms = 0.0f;
+        if (hipEventElapsedTime(&rms, c->ev[1], c->ev[3]) != hipSuccess) rms = 0.0f;
+        c->stats.rounds_ms = rms;
+        c->stats.rounds_rescan_elems = (int64_t)ctl->rounds_rescan_elems;
+        c->stats.rounds_update_elems = (int64_t)ctl->rounds_update_elems;
+    }
     c->stats.workgroups = c->pending_wgs;
     c->stats.block = c->pending_block;
     c->stats.group = c->pending_group;
@@ -708,6 +717,7 @@ int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *o
     hac::Control *ctl = reinterpret_cast<hac::Control *>(ws);
     hipError_t e = hac::launch_rounds(D, n, linkage, inst.status, ctl, ws + ro_off, G, timeout_ticks(c), rflags, s);
     if (e != hipSuccess) return hip_fail(c, e, "round kernel launch");
+    HIP_TRY(c, hipEventRecord(c->ev[3], s));
     if (handover) {
         // Resumes from the round engine's state if it hands over; its
         // records join the round engine's before they are sorted.

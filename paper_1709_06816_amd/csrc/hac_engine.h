@@ -45,6 +45,11 @@ struct Control {
     unsigned long long forced;        // extra argmin rounds forced by a row's lower bound (kFlagDefer)
     unsigned long long prof_sum[8];   // per phase, summed over workgroups (wall-clock ticks)
     unsigned long long prof_max[8];   // per phase, largest workgroup total
+    // The round engine's own share of rescans / rescan_elems / update_elems
+    // (a kernel that takes over from it adds to the fields above only).
+    unsigned long long rounds_rescans;
+    unsigned long long rounds_rescan_elems;
+    unsigned long long rounds_update_elems;
 };
 
 // One clustering instance as the engine sees it.

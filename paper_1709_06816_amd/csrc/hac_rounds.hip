@@ -497,6 +497,9 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
         atomicAdd(&ctl->rescans, rows);
         atomicAdd(&ctl->rescan_elems, re);
         atomicAdd(&ctl->update_elems, up);
+        atomicAdd(&ctl->rounds_rescans, rows);
+        atomicAdd(&ctl->rounds_rescan_elems, re);
+        atomicAdd(&ctl->rounds_update_elems, up);
     }
     if (w == 0 && tid == 0) ctl->rounds = (uint32_t)round;
     if (clk.on && tid == 0) {
