@@ -220,11 +220,17 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        (reported in hac_stats.phase_*; adds ~0.5 us per merge)
  *   HAC_OPT_BLOCK        threads per workgroup of hac_run: 256, 512 or 1024
  *                        (0 = automatic)
- *   HAC_OPT_AUTOTUNE     hac_batch picks its launch plan (threads per workgroup,
- *                        workgroups per large instance) by timing candidates on a
- *                        scratch copy of the first batch of each size mix, and
+ *   HAC_OPT_AUTOTUNE     hac_batch picks its launch plan by timing candidates on
+ *                        a scratch copy of the first batch of each size mix, and
  *                        caches the choice in the context (1 = on, the default;
- *                        0 = off).  Costs a few extra runs of that first batch.
+ *                        0 = off): threads per workgroup (256 or 1024, each with
+ *                        its own update and rescan tile sizes), then workgroups
+ *                        per large instance (1, 2, 4, 8) and the share of the
+ *                        co-resident workgroups the groups may take (a quarter,
+ *                        half, three quarters: how many of the largest
+ *                        instances get a group).  A candidate whose run reports
+ *                        an error is never chosen.  Costs eleven extra runs of
+ *                        that first batch; see hac_stats.plan_source.
  *   HAC_OPT_BATCH_BLOCK  force hac_batch's threads per workgroup: 256 or 1024
  *   HAC_OPT_BATCH_GROUP  force hac_batch's workgroups per large instance (1..64)
  *   HAC_OPT_GRAPH        hac_batch enqueues its descriptor upload, fills and
@@ -318,6 +324,12 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *                      0 otherwise
  *   rounds_rescan_elems, rounds_update_elems: that kernel's share of
  *                      rescan_elems and update_elems
+ *   plan_source:       hac_batch: 0 = default plan or one forced by
+ *                      HAC_OPT_BATCH_BLOCK / HAC_OPT_BATCH_GROUP, 1 = tuned
+ *                      during this call, 2 = the plan tuned earlier for the
+ *                      same size mix (cached in the context)
+ *   plan_share:        hac_batch with groups: quarters of the co-resident
+ *                      workgroups the groups were allowed to take (0 otherwise)
  */
 typedef struct {
     double kernel_ms;
@@ -339,6 +351,8 @@ typedef struct {
     double rounds_ms;
     int64_t rounds_rescan_elems;
     int64_t rounds_update_elems;
+    int32_t plan_source;
+    int32_t plan_share;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

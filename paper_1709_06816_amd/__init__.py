@@ -75,7 +75,8 @@ class _Stats(ctypes.Structure):
                 ("deferred", ctypes.c_int32), ("rounds", ctypes.c_int32),
                 ("handed_over", ctypes.c_int32), ("compactions", ctypes.c_int32),
                 ("rounds_ms", ctypes.c_double), ("rounds_rescan_elems", ctypes.c_int64),
-                ("rounds_update_elems", ctypes.c_int64)]
+                ("rounds_update_elems", ctypes.c_int64), ("plan_source", ctypes.c_int32),
+                ("plan_share", ctypes.c_int32)]
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")

@@ -33,6 +33,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct BatchPlan {
     int block = 256;  // threads per workgroup
     int group = 1;    // workgroups per large instance (1 = every instance on one workgroup)
+    int share = 2;    // quarters of the co-resident workgroups that groups may take
 };
 
 }  // namespace
@@ -69,6 +70,7 @@ struct hac_ctx {
     int64_t opt_defer = 1;
     int64_t opt_rounds = 1;
     int64_t opt_stall = 0;
+    int pending_plan_source = 0, pending_plan_share = 0;  // hac_batch: where its plan came from
     std::unordered_map<std::string, hipGraphExec_t> graphs;  // batch graphs by layout
 
     // State of the last enqueued call, for hac_sync / stats.
@@ -212,6 +214,8 @@ int check_status(hac_ctx *c) {
     c->stats.block = c->pending_block;
     c->stats.group = c->pending_group;
     c->stats.graph = c->pending_graph;
+    c->stats.plan_source = c->pending_plan_source;
+    c->stats.plan_share = c->pending_plan_share;
     if (c->pending_rounds && c->pending_count == 1 && (st[0] & hac::kHandover)) {
         // The round engine handed the rest of the merges to the kernel
         // queued behind it.
@@ -300,7 +304,7 @@ int batch_prepare(hac_ctx *c, float *base, const int64_t *offsets, const int32_t
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return ns[a] > ns[b]; });
 
     // Groups for the largest instances, on workgroups 0, g, 2g, ... while at
-    // most half of the co-resident workgroups are taken.
+    // most plan.share quarters of the co-resident workgroups are taken.
     const size_t lds1 = hac::lds_bytes(ns[ord[0]], hac::own_rows(ns[ord[0]], 1), true);
     int per_cu = std::max(1, hac::engine_occupancy(lds1, plan.block, true));
     int cap = per_cu * c->cus;
@@ -309,7 +313,7 @@ int batch_prepare(hac_ctx *c, float *base, const int64_t *offsets, const int32_t
     if (plan.group > 1) {
         for (int t = 0; t < count; ++t) {
             const int n = ns[ord[t]];
-            if (n < kGroupMinN || used + plan.group > cap / 2) break;
+            if (n < kGroupMinN || used + plan.group > cap * plan.share / 4) break;
             gbase.push_back(used);
             gsize.push_back(plan.group);
             used += plan.group;
@@ -356,7 +360,7 @@ int batch_prepare(hac_ctx *c, float *base, const int64_t *offsets, const int32_t
         I.n = ns[k];
         I.link = links[k];
         I.exchange = 0;
-        I.flags = c->opt_profile ? hac::kFlagProfile : 0;
+        I.flags = (c->opt_profile ? hac::kFlagProfile : 0) | (c->opt_stall ? hac::kFlagStall : 0);
     }
     for (int t = 0; t < ngroups; ++t)
         hin[ord[t]].slots = reinterpret_cast<uint64_t *>(ws + sl_off + (size_t)t * sl_each);
@@ -399,36 +403,70 @@ hipError_t batch_enqueue(hac_ctx *c, const BatchLayout &B, hipStream_t s, hipEve
     return e;
 }
 
-// Time each candidate plan once on a scratch copy of the batch and return
-// the fastest; results never depend on the plan.
+// Run `p` once on the scratch copy and return its kernel time in ms, or a
+// negative value if the plan could not be laid out or launched or if its run
+// reported any error (an instance's status word or the control block); such
+// a plan is never chosen.
+float batch_try_plan(hac_ctx *c, float *scratch, const float *packed, int64_t extent, const int64_t *offsets,
+                     const int32_t *ns, const int32_t *links, int count, hac_merge *dev_out,
+                     const int64_t *out_offsets, hipStream_t s, const BatchPlan &p) {
+    if (hipMemcpyAsync(scratch, packed, (size_t)extent * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.0f;
+    }
+    BatchLayout B;
+    if (batch_prepare(c, scratch, offsets, ns, links, count, dev_out, out_offsets, p, s, &B) != HAC_OK) return -1.0f;
+    if (batch_enqueue(c, B, s, c->ev[1]) != hipSuccess || hipEventRecord(c->ev[2], s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.0f;
+    }
+    // The control block and the status words of this run.
+    if (hipMemcpy(c->pinned, c->ws, B.st_off + (size_t)count * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.0f;
+    }
+    const hac::Control *ctl = reinterpret_cast<const hac::Control *>(c->pinned);
+    const uint32_t *st = reinterpret_cast<const uint32_t *>(static_cast<const char *>(c->pinned) + B.st_off);
+    if (ctl->error || ctl->abort) return -1.0f;
+    for (int k = 0; k < count; ++k)
+        if (st[k]) return -1.0f;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) != hipSuccess) return -1.0f;
+    return ms;
+}
+
+// Pick a launch plan by timing candidates on a scratch copy of the batch;
+// results never depend on the plan.  Coordinate search: first the threads
+// per workgroup with every instance on one workgroup (each block size
+// carries its own tile sizes: 8-deep update batches and 8-load rescan
+// segments per lane at 256 threads, 2 and 4 at 1024), then with that block
+// size the workgroups per large instance (2, 4, 8) and how many of the
+// co-resident workgroups groups may take (a quarter, half, three quarters),
+// which decides how many of the largest instances get a group.  Plans whose
+// run reports an error are skipped; if every plan fails, the default plan is
+// kept and the real run reports the error.
 int batch_autotune(hac_ctx *c, float *packed, int64_t extent, const int64_t *offsets,
                    const int32_t *ns, const int32_t *links, int count, hac_merge *dev_out,
                    const int64_t *out_offsets, hipStream_t s, BatchPlan *best) {
-    const BatchPlan cands[] = {{256, 1}, {1024, 1}, {256, 4}, {256, 8}, {1024, 4}, {1024, 8}};
     float *scratch = nullptr;
     size_t scratch_cap = 0;
     int rc = ensure_dev(c, reinterpret_cast<void **>(&scratch), &scratch_cap, (size_t)extent * 4, "tuning copy");
     if (rc) return rc;
     float best_ms = 1e30f;
-    *best = cands[0];
-    for (const BatchPlan &p : cands) {
-        hipError_t e = hipMemcpyAsync(scratch, packed, (size_t)extent * 4, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) break;
-        BatchLayout B;
-        if (batch_prepare(c, scratch, offsets, ns, links, count, dev_out, out_offsets, p, s, &B) != HAC_OK)
-            continue;
-        e = batch_enqueue(c, B, s, c->ev[1]);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            continue;
-        }
-        if (hipEventRecord(c->ev[2], s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) break;
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess && ms < best_ms) {
+    *best = BatchPlan{};
+    auto consider = [&](const BatchPlan &p) {
+        const float ms = batch_try_plan(c, scratch, packed, extent, offsets, ns, links, count, dev_out, out_offsets,
+                                        s, p);
+        if (ms >= 0.0f && ms < best_ms) {
             best_ms = ms;
             *best = p;
         }
-    }
+    };
+    for (int block : {256, 1024}) consider(BatchPlan{block, 1, 2});
+    const int block = best->block;
+    for (int group : {2, 4, 8})
+        for (int share : {1, 2, 3}) consider(BatchPlan{block, group, share});
     (void)hipStreamSynchronize(s);
     (void)hipFree(scratch);
     c->err.clear();
@@ -736,6 +774,7 @@ int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *o
     c->pending_block = hac::kRoundsBlock;
     c->pending_group = G;
     c->pending_graph = 0;
+    c->pending_plan_source = c->pending_plan_share = 0;
     c->pending_deferred = 0;
     c->pending_rounds = true;
     c->pending_seq_wgs = g;
@@ -800,6 +839,7 @@ int run_scan(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     c->pending_block = hac::kScanBlock;
     c->pending_group = G;
     c->pending_graph = 0;
+    c->pending_plan_source = c->pending_plan_share = 0;
     c->pending_deferred = 0;
     c->pending_scan = true;
     return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
@@ -897,6 +937,7 @@ int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     c->pending_block = block;
     c->pending_group = g;
     c->pending_graph = 0;
+    c->pending_plan_source = c->pending_plan_share = 0;
     c->pending_deferred = (run_flags & hac::kFlagDefer) ? 1 : 0;
     if (noalloc) return finish(c, s, 1, nullptr, 0, flags, ws);
     return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
@@ -972,6 +1013,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
 
     // Plan: forced by options, cached for this size mix, or tuned now.
     BatchPlan plan;
+    int plan_source = 0;  // 0: default or forced by options, 1: tuned now, 2: tuned earlier (cached)
     if (c->opt_batch_block > 0 || c->opt_batch_group > 0) {
         if (c->opt_batch_block > 0) plan.block = (int)c->opt_batch_block;
         if (c->opt_batch_group > 0) plan.group = (int)c->opt_batch_group;
@@ -980,10 +1022,12 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         auto it = c->plans.find(sig);
         if (it != c->plans.end()) {
             plan = it->second;
+            plan_source = 2;
         } else if (c->opt_autotune && count >= 8) {
             rc = batch_autotune(c, base, extent, offsets, ns, linkages, count, dev_out, out_offsets, s, &plan);
             if (rc) return rc;
             c->plans[sig] = plan;
+            plan_source = 1;
         }
     }
 
@@ -1023,6 +1067,8 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->pending_wgs = B.L.grid;
     c->pending_block = plan.block;
     c->pending_group = B.group;
+    c->pending_plan_source = plan_source;
+    c->pending_plan_share = B.group > 1 ? plan.share : 0;
     c->pending_graph = graphed;
     c->pending_deferred = 0;
     c->pending_rounds = false;

@@ -51,3 +51,34 @@ def test_stalled_exchange_times_out_and_recovers(ctx, rounds, link):
         assert got.tobytes() == oracle.run_f32(d, link).tobytes()
     finally:
         ctx.set_option(hac.OPT_ROUNDS, 1)
+
+
+def test_autotune_never_picks_a_failing_plan(ctx):
+    """hac_batch's autotuner reads every candidate's status words: with the
+    first exchange of every group withheld (HAC_OPT_INJECT_STALL) and a short
+    watchdog, each plan with groups ends in a timeout, so the tuner must pick
+    a plan without groups; the call then succeeds with the oracle's lists."""
+    import torch
+    spec = synth.batch_spec(count=12, n_lo=64, n_hi=1024, seed=515)
+    ns = spec.ns.copy()
+    ns[:2] = [2600, 2100]  # instances that qualify for groups
+    mats = [synth.batch_instance(int(n), int(s)) for n, s in zip(ns, spec.seeds)]
+    offs, total = synth.pack_offsets(ns)
+    packed = np.zeros(total, np.float32)
+    for k, m in enumerate(mats):
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+    t = torch.from_numpy(packed).cuda()
+    ctx.set_option(hac.OPT_TIMEOUT_MS, 50)
+    ctx.set_option(hac.OPT_INJECT_STALL, 1)
+    try:
+        print("failure: autotuning with stalled group exchanges", flush=True)
+        res = ctx.batch(t, offs, ns, spec.linkages, preserve=True)
+        st = ctx.stats()
+    finally:
+        ctx.set_option(hac.OPT_INJECT_STALL, 0)
+        ctx.set_option(hac.OPT_TIMEOUT_MS, 0)
+    assert st["plan_source"] == 1 and st["group"] == 1
+    moff, _ = synth.merge_offsets(ns)
+    for k in range(len(ns)):
+        n = int(ns[k])
+        assert res[moff[k]:moff[k] + n - 1].tobytes() == oracle.run_f32(mats[k], int(spec.linkages[k])).tobytes(), k

@@ -373,9 +373,13 @@ def test_batch_plans_identical(ctx, torch):
     _say("batch autotuned")
     res = ctx.batch(t, offs, ns, spec.linkages, preserve=True)
     assert _same(res, ref)
-    assert ctx.stats()["block"] in (256, 1024)
+    st = ctx.stats()
+    assert st["block"] in (256, 1024) and st["plan_source"] == 1
+    assert st["plan_share"] in ((1, 2, 3) if st["group"] > 1 else (0,))
     res = ctx.batch(t, offs, ns, spec.linkages, preserve=True)  # cached plan
     assert _same(res, ref)
+    st2 = ctx.stats()
+    assert st2["plan_source"] == 2 and (st2["block"], st2["group"]) == (st["block"], st["group"])
     assert np.array_equal(t.cpu().numpy(), packed)
     moff, _ = synth.merge_offsets(ns)
     for k in range(3):
