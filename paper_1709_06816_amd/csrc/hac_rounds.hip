@@ -58,7 +58,7 @@ namespace {
 constexpr uint64_t kNone = ~0ull;
 constexpr int B = kRoundsBlock;
 constexpr int W = B / 64;
-constexpr int kPairsPerUnit = 64;   // pairs one wave applies to its 64 columns
+constexpr int kPairsPerUnit = 64;   // most pairs one wave applies to its 64 columns
 constexpr int kUnroll = 4;          // pairs in flight per lane
 constexpr int kMaskWords = (HAC_MAX_N + 31) / 32;
 
@@ -387,7 +387,14 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
                     V.cw[s_pair[t].x] = kNoCount;
                 }
             const int extra_i = np > p0 ? s_pair[p0].x : -1, extra_j = np > p0 ? s_pair[p0].y : -1;
-            const int npr = (np + kPairsPerUnit - 1) / kPairsPerUnit;
+            // Pairs per unit: as few as spread the round's (pair, 64-column
+            // block) work over every wave of the grid, so that a round with
+            // few pairs still keeps all waves busy and the slowest wave, which
+            // every workgroup waits for at the next barrier, has no more than
+            // its share.
+            const int per_wave = (int)(((int64_t)np * nblocks + NW - 1) / NW);
+            const int ppu = min(kPairsPerUnit, max(kUnroll, (per_wave + kUnroll - 1) / kUnroll * kUnroll));
+            const int npr = (np + ppu - 1) / ppu;
             const int units = nblocks * npr;
             for (int u = gw; u < units; u += NW) {
                 const int cb = u % nblocks, pr = u / nblocks;
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
                 const uint64_t ec = (lv && rl == 0) ? V.rk[c] : kNone;
                 const uint32_t valc = value_of(ec);
                 const int pic = partner_of(ec);
-                const int pb = pr * kPairsPerUnit, pe = min(np, pb + kPairsPerUnit);
+                const int pb = pr * ppu, pe = min(np, pb + ppu);
                 for (int p = pb; p < pe; p += kUnroll) {
                     float a[kUnroll], b[kUnroll];
 #pragma unroll
