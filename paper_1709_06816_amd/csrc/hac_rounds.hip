@@ -34,12 +34,13 @@
 //      claims the reciprocal (and, for single, strict) pairs, writes their
 //      merge records, and publishes its rows' smallest pair key.
 //   B  update: every workgroup loads the round's pairs (plus the global
-//      smallest key if it was not claimed) and takes (64 columns x 64 pairs)
-//      units: v = min/max(D[i][c], D[j][c]) written to both D[i][c] and
-//      D[c][i].  Entries between two clusters merged in the same round get
-//      contributions from four lanes (columns i_q and j_q of pair p and
-//      vice versa) combined with atomic min/max, which is idempotent, so the
-//      result is the same whatever the interleaving.  Rows whose cached
+//      smallest key if it was not claimed) and takes (64 columns x up to 64
+//      pairs) units over the columns of clusters not merged this round:
+//      v = min/max(D[i][c], D[j][c]) written to both D[i][c] and D[c][i].
+//      The entry between two clusters merged in the same round, p and q, is
+//      min/max of the four entries between their members, computed once by
+//      one thread per unordered pair {p, q}; no other thread of the phase
+//      touches those entries.  Rows whose cached
 //      partner merged: complete -> queued for a rescan; single -> the
 //      partner moves to i (the value cannot change) and the count of
 //      entries equal to the minimum drops when both merged entries had it.
@@ -67,20 +68,6 @@ __device__ __forceinline__ uint32_t value_of(uint64_t e) { return (uint32_t)(e >
 
 __device__ __forceinline__ float lw_minmax(int link, float a, float b) {
     return link == HAC_SINGLE ? fminf(a, b) : fmaxf(a, b);
-}
-
-// *p = min/max(*p, v) (single / complete), agent scope.
-__device__ void atomic_minmax(float *p, float v, int link) {
-    uint32_t *q = reinterpret_cast<uint32_t *>(p);
-    uint32_t cur = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        const float c = __uint_as_float(cur);
-        const float nv = lw_minmax(link, c, v);
-        if (__float_as_uint(nv) == cur) return;
-        if (__hip_atomic_compare_exchange_strong(q, &cur, __float_as_uint(nv), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
-            return;
-    }
 }
 
 __shared__ uint32_t s_live[kMaskWords];          // live bitmask of all slots (same on every workgroup)
@@ -399,13 +386,12 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
             for (int u = gw; u < units; u += NW) {
                 const int cb = u % nblocks, pr = u / nblocks;
                 const int c = cb * 64 + lane;
-                const bool lv = c < n && live_at(c);
+                // Columns of the round's own clusters are left to the pass
+                // below: their entries are between two merged clusters.
+                bool lv = c < n && live_at(c) && c != extra_i && c != extra_j;
+                if (lv && V.role[c] != 0) lv = false;
                 if (__ballot(lv) == 0ull) continue;
-                int rl = lv ? V.role[c] : 0;
-                if (c == extra_i) rl = p0 + 1;
-                if (c == extra_j) rl = -(p0 + 1);
-                const int q = rl > 0 ? rl - 1 : -rl - 1;  // this column's own pair (rl != 0)
-                const uint64_t ec = (lv && rl == 0) ? V.rk[c] : kNone;
+                const uint64_t ec = lv ? V.rk[c] : kNone;
                 const uint32_t valc = value_of(ec);
                 const int pic = partner_of(ec);
                 const int pb = pr * ppu, pe = min(np, pb + ppu);
@@ -414,7 +400,7 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
 #pragma unroll
                     for (int t = 0; t < kUnroll; ++t) {
                         const int pp = p + t;
-                        const bool use = lv && pp < pe && !(rl != 0 && q == pp);
+                        const bool use = lv && pp < pe;
                         const int2 ij = s_pair[pp < pe ? pp : pb];
                         a[t] = use ? D[(size_t)ij.x * n + c] : 0.0f;
                         b[t] = use ? D[(size_t)ij.y * n + c] : 0.0f;
@@ -422,37 +408,50 @@ __global__ __launch_bounds__(kRoundsBlock) void k_rounds(float *D, int n, int li
 #pragma unroll
                     for (int t = 0; t < kUnroll; ++t) {
                         const int pp = p + t;
-                        if (!lv || pp >= pe || (rl != 0 && q == pp)) continue;
+                        if (!lv || pp >= pe) continue;
                         const int2 ij = s_pair[pp];
                         float v = lw_minmax(link, a[t], b[t]);
                         if (v == 0.0f) v = 0.0f;
-                        if (rl == 0) {
-                            D[(size_t)ij.x * n + c] = v;
-                            D[(size_t)c * n + ij.x] = v;
-                            ++st_upd;
-                            if (link == HAC_COMPLETE) {
-                                if (pic == ij.x || pic == ij.y) {
-                                    // The row's minimum went up or away: rescan it.
-                                    V.rk[c] = kNone;
-                                    V.cw[c] = kNoCount;
-                                    V.resc[atomicAdd(&V.rc->resc, 1u)] = c;
-                                }
-                            } else {
-                                if (ord32(v) == valc)
-                                    atomicMin(reinterpret_cast<unsigned long long *>(V.rk + c),
-                                              (unsigned long long)(((uint64_t)valc << 32) | ((uint64_t)ij.x << 16)));
-                                if (ord32(a[t]) == valc && ord32(b[t]) == valc)
-                                    atomicSub(reinterpret_cast<unsigned long long *>(V.cw + c), 1ull);
+                        D[(size_t)ij.x * n + c] = v;
+                        D[(size_t)c * n + ij.x] = v;
+                        ++st_upd;
+                        if (link == HAC_COMPLETE) {
+                            if (pic == ij.x || pic == ij.y) {
+                                // The row's minimum went up or away: rescan it.
+                                V.rk[c] = kNone;
+                                V.cw[c] = kNoCount;
+                                V.resc[atomicAdd(&V.rc->resc, 1u)] = c;
                             }
                         } else {
-                            // Column c is i_q or j_q of another pair q: its part of
-                            // the entry between the two merged clusters.
-                            const int iq = s_pair[q].x;
-                            atomic_minmax(D + (size_t)ij.x * n + iq, v, link);
-                            atomic_minmax(D + (size_t)iq * n + ij.x, v, link);
+                            if (ord32(v) == valc)
+                                atomicMin(reinterpret_cast<unsigned long long *>(V.rk + c),
+                                          (unsigned long long)(((uint64_t)valc << 32) | ((uint64_t)ij.x << 16)));
+                            if (ord32(a[t]) == valc && ord32(b[t]) == valc)
+                                atomicSub(reinterpret_cast<unsigned long long *>(V.cw + c), 1ull);
                         }
                     }
                 }
+            }
+            // Entries between two clusters merged in this round: the new
+            // distance of (i_p + j_p, i_q + j_q) is min / max of the four
+            // entries between their members, exact and in any order.  One
+            // thread per unordered pair of pairs reads the four and writes
+            // both copies; nothing else in this phase reads or writes them.
+            const int64_t ncross = (int64_t)np * (np - 1) / 2;
+            for (int64_t t = (int64_t)w * B + tid; t < ncross; t += (int64_t)G * B) {
+                // t -> (p, q), p < q: row q of the strict lower triangle
+                // holds t in [q(q-1)/2, q(q+1)/2).
+                int q = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+                while ((int64_t)q * (q - 1) / 2 > t) --q;
+                while ((int64_t)(q + 1) * q / 2 <= t) ++q;
+                const int p = (int)(t - (int64_t)q * (q - 1) / 2);
+                const int2 P = s_pair[p], Q = s_pair[q];
+                const float v = lw_minmax(link, lw_minmax(link, D[(size_t)P.x * n + Q.x], D[(size_t)P.y * n + Q.x]),
+                                          lw_minmax(link, D[(size_t)P.x * n + Q.y], D[(size_t)P.y * n + Q.y]));
+                const float vz = v == 0.0f ? 0.0f : v;
+                D[(size_t)P.x * n + Q.x] = vz;
+                D[(size_t)Q.x * n + P.x] = vz;
+                ++st_upd;
             }
         }
         clk.lap(2);
