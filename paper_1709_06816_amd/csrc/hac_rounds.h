@@ -10,7 +10,7 @@
 namespace hac {
 
 constexpr int kRoundsBlock = 1024;     // threads per workgroup of the round kernel
-constexpr int kRoundsMaxPairs = 1024;  // pairs merged in one round at most
+constexpr int kRoundsMaxPairs = 2048;  // pairs merged in one round at most
 
 // Control block of a round-engine launch (device memory, zeroed before it).
 struct RoundsCtl {

@@ -84,13 +84,21 @@ def test_rounds_constant_matrix(ctx, link):
 
 @pytest.mark.parametrize("link", ["single", "complete"])
 def test_rounds_more_pairs_than_one_round_takes(ctx, link):
-    # n=8192 mixture: the first rounds offer more reciprocal pairs than a
-    # round merges (1024); the rest wait for later rounds.
-    d = synth.mixture_8192(seed=5, n=8192)
-    print("rounds: mixture n=8192 %s" % link, flush=True)
-    got, st = _run(ctx, d, link)
-    assert got.tobytes() == oracle.run_f32(d, link).tobytes()
-    assert st["rounds"] < 8191 // 8
+    # 4096 tight pairs of points far apart (n=8192): the first round offers
+    # 4096 reciprocal pairs, more than a round merges (2048); the rest wait
+    # for the next round.  Then the n=8192 mixture.
+    rng = np.random.default_rng(5)
+    centres = rng.uniform(-100.0, 100.0, size=(4096, 16))
+    pts = np.repeat(centres, 2, axis=0) + rng.normal(0.0, 0.01, size=(8192, 16))
+    # Past the first rounds the tight-pairs input is 4096 points spread
+    # uniformly, on which single linkage chains (few reciprocal pairs per
+    # round): the round bound is looser there.
+    for name, d, bound in (("tight pairs", synth.euclidean_matrix(pts), 8191 // 2),
+                           ("mixture", synth.mixture_8192(seed=5, n=8192), 8191 // 8)):
+        print("rounds: %s n=8192 %s" % (name, link), flush=True)
+        got, st = _run(ctx, d, link)
+        assert got.tobytes() == oracle.run_f32(d, link).tobytes()
+        assert st["rounds"] < bound, (name, st["rounds"])
 
 
 def test_rounds_input_errors_and_flags(ctx):
