@@ -269,6 +269,16 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        expire after HAC_OPT_TIMEOUT_MS, every workgroup leaves
  *                        the kernel and the call returns HAC_ETIMEDOUT (out
  *                        unspecified).  0 (the default) = off.
+ *   HAC_OPT_LAZY_MIRROR  hac_batch, and servers created afterwards: 1 (the
+ *                        default) = the Lance-Williams update writes only the
+ *                        survivor's row, not the mirrored column, and each
+ *                        workgroup remembers the merge step that last wrote
+ *                        every row, so that a pair's current distance is read
+ *                        from whichever of its two rows was written later
+ *                        (instances whose step table does not fit the LDS
+ *                        write both halves); 0 = always write both halves.
+ *                        Results are identical either way; the working
+ *                        matrix's contents afterwards are unspecified.
  */
 typedef enum {
     HAC_OPT_WORKGROUPS = 1,
@@ -283,7 +293,8 @@ typedef enum {
     HAC_OPT_GRAPH = 10,
     HAC_OPT_DEFER = 11,
     HAC_OPT_ROUNDS = 12,
-    HAC_OPT_INJECT_STALL = 13
+    HAC_OPT_INJECT_STALL = 13,
+    HAC_OPT_LAZY_MIRROR = 14
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 

@@ -40,6 +40,7 @@ OPT_AUTOTUNE, OPT_BATCH_BLOCK, OPT_BATCH_GROUP, OPT_GRAPH = 7, 8, 9, 10
 OPT_DEFER = 11
 OPT_ROUNDS = 12
 OPT_INJECT_STALL = 13
+OPT_LAZY_MIRROR = 14
 MAX_N = 65536
 MAX_BATCH_N = 8192
 NOALLOC_MAX_N = 65536

@@ -70,6 +70,7 @@ struct hac_ctx {
     int64_t opt_defer = 1;
     int64_t opt_rounds = 1;
     int64_t opt_stall = 0;
+    bool opt_lazy = true;  // HAC_OPT_LAZY_MIRROR
     int pending_plan_source = 0, pending_plan_share = 0;  // hac_batch: where its plan came from
     std::unordered_map<std::string, hipGraphExec_t> graphs;  // batch graphs by layout
 
@@ -320,12 +321,14 @@ int batch_prepare(hac_ctx *c, float *base, const int64_t *offsets, const int32_t
         }
     }
     const int ngroups = (int)gbase.size();
+    // An instance uses the lazy mirror if its step table fits beside the rest.
+    std::vector<uint8_t> lazy(count, 0);
     size_t lds = 0;
     for (int t = 0; t < count; ++t) {
-        const int n = ns[ord[t]], g = t < ngroups ? plan.group : 1;
-        lds = std::max(lds, hac::lds_bytes(n, hac::own_rows(n, g), true));
+        const int n = ns[ord[t]], g = t < ngroups ? plan.group : 1, own = hac::own_rows(n, g);
+        lazy[ord[t]] = c->opt_lazy && hac::lds_bytes(n, own, true, true) <= c->lds_max;
+        lds = std::max(lds, hac::lds_bytes(n, own, true, lazy[ord[t]] != 0));
         if (lds > c->lds_max) return fail(c, HAC_EINVAL, "n=%d does not fit one workgroup's LDS", n);
-        if (t >= ngroups) break;  // the rest are no larger than this one
     }
     per_cu = std::max(1, hac::engine_occupancy(lds, plan.block, true));
     cap = per_cu * c->cus;
@@ -360,7 +363,8 @@ int batch_prepare(hac_ctx *c, float *base, const int64_t *offsets, const int32_t
         I.n = ns[k];
         I.link = links[k];
         I.exchange = 0;
-        I.flags = (c->opt_profile ? hac::kFlagProfile : 0) | (c->opt_stall ? hac::kFlagStall : 0);
+        I.flags = (c->opt_profile ? hac::kFlagProfile : 0) | (c->opt_stall ? hac::kFlagStall : 0) |
+                  (lazy[k] ? hac::kFlagLazy : 0);
     }
     for (int t = 0; t < ngroups; ++t)
         hin[ord[t]].slots = reinterpret_cast<uint64_t *>(ws + sl_off + (size_t)t * sl_each);
@@ -482,6 +486,7 @@ void ctx_info(const hac_ctx *c, CtxInfo *out) {
     out->wallclock_khz = c->wallclock_khz;
     out->lds_max = c->lds_max;
     out->timeout_ms = c->opt_timeout_ms;
+    out->lazy = c->opt_lazy;
 }
 }  // namespace hac
 
@@ -604,6 +609,7 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
     case HAC_OPT_AUTOTUNE: c->opt_autotune = value != 0; return HAC_OK;
     case HAC_OPT_GRAPH: c->opt_graph = value != 0; return HAC_OK;
     case HAC_OPT_INJECT_STALL: c->opt_stall = value != 0; return HAC_OK;
+    case HAC_OPT_LAZY_MIRROR: c->opt_lazy = value != 0; return HAC_OK;
     case HAC_OPT_ROUNDS:
         if (value > 2) return fail(c, HAC_EINVAL, "rounds mode %lld is not 0, 1 or 2", (long long)value);
         c->opt_rounds = value;

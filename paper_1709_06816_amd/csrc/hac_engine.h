@@ -74,6 +74,9 @@ enum : int32_t {
     kFlagNoHandover = 16,  // round engine: never hand over, rounds to the end (HAC_OPT_ROUNDS = 2)
     kFlagStall = 32,       // failure test: workgroup 0 never publishes, so the other
                            // workgroups' bounded waits expire (HAC_OPT_INJECT_STALL)
+    kFlagLazy = 64,        // lazy mirror (batch and serving kernels): the update writes row i
+                           // only, and a pair's current value is read from the one of its two
+                           // rows written last (write steps in LDS); needs lds_bytes(.., true)
 };
 
 // State left by the round engine when it hands an instance over part-way
@@ -90,8 +93,9 @@ struct Resume {
 // Rows a workgroup owns when g workgroups share n items.
 int own_rows(int n, int g);
 // Bytes of dynamic LDS one workgroup needs to own `own` rows of an n-item
-// instance; `in_kernel_setup` adds room for the mirror tile (batch kernel).
-size_t lds_bytes(int n, int own, bool in_kernel_setup);
+// instance; `in_kernel_setup` adds room for the mirror tile (batch kernel),
+// `lazy` for the row write steps of kFlagLazy.
+size_t lds_bytes(int n, int own, bool in_kernel_setup, bool lazy = false);
 
 // Fill `words` u32 with zero on `stream` (a kernel, not a memset node).
 hipError_t launch_zero(void *p, size_t words, hipStream_t stream);

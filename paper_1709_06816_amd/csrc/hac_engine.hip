@@ -337,17 +337,27 @@ struct Lds {
     uint16_t *rlist;    // own_cap entries: rows queued for a rescan (local index)
     uint32_t *amask;    // live bitmask of all n slots
     uint16_t *size1;    // size - 1 of every slot's cluster (n entries)
-    float *tile;        // mirror tile (in-kernel set-up only; shares space with size1)
+    uint16_t *wstep;    // lazy mirror: merge step (from 1) that last wrote each slot's row,
+                        // 0 for the input (n entries, 8-byte aligned); null otherwise
+    float *tile;        // mirror tile (in-kernel set-up only; shares space with size1, wstep)
 };
 
-__device__ Lds carve(uint8_t *smem, int n, int own_cap) {
+__device__ Lds carve(uint8_t *smem, int n, int own_cap, bool lazy) {
     Lds L;
     L.cache = reinterpret_cast<uint64_t *>(smem);
     L.rlist = reinterpret_cast<uint16_t *>(L.cache + own_cap);
     L.amask = reinterpret_cast<uint32_t *>(L.rlist + own_cap);
     L.size1 = reinterpret_cast<uint16_t *>(L.amask + (((n + 31) >> 5) + 3) / 4 * 4);
+    L.wstep = lazy ? L.size1 + ((n + 3) & ~3) : nullptr;
     L.tile = reinterpret_cast<float *>(L.size1);
     return L;
+}
+
+// Lazy mirror: where pair (a, b)'s current value is.  A merge step writes the
+// whole row of its survivor, so of the two rows the one written last holds
+// it; rows never written hold the (mirrored) input.
+__device__ __forceinline__ size_t pair_at(int a, int b, uint32_t ta, uint32_t tb, int n) {
+    return tb > ta ? (size_t)b * n + a : (size_t)a * n + b;
 }
 
 template <int B>
@@ -358,6 +368,8 @@ __device__ void init_masks(const Lds &L, int n) {
         L.amask[q] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
     }
     for (int k = threadIdx.x; k < n; k += B) L.size1[k] = 0;
+    if (L.wstep)
+        for (int k = threadIdx.x; k < n; k += B) L.wstep[k] = 0;
 }
 
 // Minimum (D[k][l], l) over live l > k, l != skip, of row k, folded into the
@@ -365,9 +377,11 @@ __device__ void init_masks(const Lds &L, int n) {
 // per lane), and waves WV0 .. B/64-1 take segments round-robin starting at
 // wave (WV0 + base) mod their number (so consecutive rows start on different
 // waves).  Returns the number of segments.  Waves below WV0 only count.
+// With `wstep` (lazy mirror) each entry is read where pair_at puts it: from
+// row k, or from row l if that was written later.
 template <int B, int WV0, int U = seg_unroll<B>()>
 __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_t *amask, int skip, int base,
-                        uint64_t *acc, unsigned long long &elems) {
+                        uint64_t *acc, unsigned long long &elems, const uint16_t *wstep) {
     constexpr int W = B / 64 - WV0;
     static_assert(W >= 1, "no wave left to rescan");
     const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6) - WV0;
@@ -379,12 +393,31 @@ __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_
         const int q0 = (k + 1) >> 2, nq = n >> 2;
         nseg = (nq - q0 + 64 * U - 1) / (64 * U);
         if (wv < 0) return nseg;
+        const uint32_t tk = wstep ? wstep[k] : 0u;
         for (int sg = first_sg; sg < nseg; sg += W) {
             float4 x[U];
+            if (wstep) {
+                // One 4-byte load per entry; the four write steps of a quad
+                // come from one 8-byte LDS read.
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int q = q0 + sg * 64 * U + u * 64 + lane;
-                x[u] = q < nq ? *reinterpret_cast<const float4 *>(row + 4 * q) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                for (int u = 0; u < U; ++u) {
+                    const int q = q0 + sg * 64 * U + u * 64 + lane;
+                    float e[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (q < nq) {
+                        const uint64_t t4 = *reinterpret_cast<const uint64_t *>(wstep + 4 * q);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            e[c] = D[pair_at(k, 4 * q + c, tk, (uint32_t)(t4 >> (16 * c)) & 0xFFFFu, n)];
+                    }
+                    x[u] = make_float4(e[0], e[1], e[2], e[3]);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = q0 + sg * 64 * U + u * 64 + lane;
+                    x[u] = q < nq ? *reinterpret_cast<const float4 *>(row + 4 * q)
+                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
             }
             uint64_t best = kEmpty;
 #pragma unroll
@@ -408,12 +441,13 @@ __device__ int scan_row(const float *__restrict__ D, int n, int k, const uint32_
         const int l0 = k + 1;
         nseg = (n - l0 + 64 * U - 1) / (64 * U);
         if (wv < 0) return nseg;
+        const uint32_t tk = wstep ? wstep[k] : 0u;
         for (int sg = first_sg; sg < nseg; sg += W) {
             float x[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int l = l0 + sg * 64 * U + u * 64 + lane;
-                x[u] = l < n ? row[l] : 0.0f;
+                x[u] = l >= n ? 0.0f : wstep ? D[pair_at(k, l, tk, wstep[l], n)] : row[l];
             }
             uint64_t best = kEmpty;
 #pragma unroll
@@ -441,7 +475,7 @@ __device__ void rescan_rows(const float *__restrict__ D, int n, int g, int w, co
     int base = 0;
     for (uint32_t r = 0; r < nresc; ++r) {
         const int li = L.rlist[r];
-        base += scan_row<B, 0>(D, n, row_of_local(li, g, w), L.amask, skip, base, &L.cache[li], elems);
+        base += scan_row<B, 0>(D, n, row_of_local(li, g, w), L.amask, skip, base, &L.cache[li], elems, L.wstep);
     }
 }
 
@@ -503,6 +537,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
     const int own_ch = own_chunks(n, g, w);
     const bool prof = (I.flags & kFlagProfile) != 0;
+    const bool lazy = L.wstep != nullptr;
     float *D = I.D;
 
     if (tid == 0) {
@@ -612,15 +647,18 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         if (s == n - 2) break;
 
         // ---- loads of rows i and j for the first batch of owned columns ---
+        // (lazy mirror: D_ik from row i or from row k, whichever was written
+        // last; without it both steps are 0 and the row is read)
         float *Di = D + (size_t)i * n;
-        const float *Dj = D + (size_t)j * n;
+        const uint32_t ti = lazy ? L.wstep[i] : 0u, tj = lazy ? L.wstep[j] : 0u;
         float a[U], bv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int lq = wv + u * W;
             const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-            a[u] = k < n ? Di[k] : 0.0f;
-            bv[u] = k < n ? Dj[k] : 0.0f;
+            const uint32_t tk = lazy && k < n ? L.wstep[k] : 0u;
+            a[u] = k < n ? D[pair_at(i, k, ti, tk, n)] : 0.0f;
+            bv[u] = k < n ? D[pair_at(j, k, tj, tk, n)] : 0.0f;
         }
         // ---- retire j (Section 5.3 step 6); queue rows whose partner is i or j
         if (tid == 0) {
@@ -672,8 +710,9 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 for (int u = 0; u < U; ++u) {
                     const int lq = lq0 + u * W;
                     const int k = lq < own_ch ? chunk_of(lq, g, w) * 64 + lane : n;
-                    a[u] = k < n ? Di[k] : 0.0f;
-                    bv[u] = k < n ? Dj[k] : 0.0f;
+                    const uint32_t tk = lazy && k < n ? L.wstep[k] : 0u;
+                    a[u] = k < n ? D[pair_at(i, k, ti, tk, n)] : 0.0f;
+                    bv[u] = k < n ? D[pair_at(j, k, tj, tk, n)] : 0.0f;
                 }
             }
 #pragma unroll
@@ -684,6 +723,8 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                 if (k >= n || k == i || k == j || !is_live(L.amask, k)) continue;
                 const int nk = link == HAC_WARD ? (int)L.size1[k] + 1 : 1;
                 const float v = lw_update(link, a[u], bv[u], h, ni, nj, nk, ai, aj, bij);
+                // The column half D[k][i] is written only without the lazy
+                // mirror (with it, row i is now the later-written copy).
                 if (g > 1) {
                     // Other workgroups read these entries after the next
                     // exchange: agent-scope stores put them at the device's
@@ -691,11 +732,12 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
                     // back (which would wait for every dirty line of the XCD).
                     __hip_atomic_store(reinterpret_cast<uint32_t *>(Di + k), __float_as_uint(v), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(reinterpret_cast<uint32_t *>(D + (size_t)k * n + i), __float_as_uint(v),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (!lazy)
+                        __hip_atomic_store(reinterpret_cast<uint32_t *>(D + (size_t)k * n + i), __float_as_uint(v),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     Di[k] = v;
-                    D[(size_t)k * n + i] = v;
+                    if (!lazy) D[(size_t)k * n + i] = v;
                 }
                 st.update_elems++;
                 const uint64_t key = ((uint64_t)ord32(v) << 32) | ((uint64_t)i << 16);
@@ -735,6 +777,7 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         // this merge, and nothing reads them again before the next one.
         if (tid == 0) {
             L.size1[i] = (uint16_t)(ni + nj - 1);
+            if (lazy) L.wstep[i] = (uint16_t)(s + 1);  // read again only after the next barrier
             st.rescans += nresc;
             s_nresc = 0;
         }
@@ -814,7 +857,7 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
     if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
     const int g = (int)gridDim.x, w = (int)blockIdx.x, n = I.n;
     const int own_cap = ((((n + 63) >> 6) + g - 1) / g) * 64;
-    const Lds L = carve(smem, n, own_cap);
+    const Lds L = carve(smem, n, own_cap, false);
     // The set-up kernel (and the round engine, if queued behind it) has
     // finished: the status word is final and the same for every thread of
     // every workgroup.
@@ -868,7 +911,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     if (threadIdx.x == 0 && (I.flags & kFlagProfile)) st.mark = wall_clock64();
     const int own_ch = own_chunks(n, g, w);
     const int own_cap = ((((n + 63) >> 6) + g - 1) / g) * 64;
-    const Lds L = carve(smem, n, own_cap);
+    const Lds L = carve(smem, n, own_cap, (I.flags & kFlagLazy) != 0);
     for (int li = threadIdx.x; li < own_cap; li += B) L.cache[li] = kEmptyRow;
     __syncthreads();
     uint32_t bad = 0;
@@ -1167,11 +1210,11 @@ hipError_t engine_scratch(void **ptr) { return hipGetSymbolAddress(ptr, HIP_SYMB
 
 int own_rows(int n, int g) { return ((((n + 63) >> 6) + g - 1) / g) * 64; }
 
-size_t lds_bytes(int n, int own, bool in_kernel_setup) {
+size_t lds_bytes(int n, int own, bool in_kernel_setup, bool lazy) {
     const size_t mask = (((size_t)(n + 31) / 32 + 3) / 4 * 4) * 4;
-    const size_t size1 = (size_t)n * 2;
+    const size_t sizes = lazy ? (size_t)((n + 3) & ~3) * 2 + (size_t)n * 2 : (size_t)n * 2;  // size1 (+ wstep)
     const size_t tile = in_kernel_setup ? (size_t)kTile * (kTile + 1) * 4 : 0;
-    return (size_t)own * 8 + (size_t)own * 2 + mask + (size1 > tile ? size1 : tile);
+    return (size_t)own * 8 + (size_t)own * 2 + mask + (sizes > tile ? sizes : tile);
 }
 
 template <int B>

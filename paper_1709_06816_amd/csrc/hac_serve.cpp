@@ -66,6 +66,7 @@ struct Job {
     const float *src_dev = nullptr;  // device address of page-locked input, or null (staged)
     int64_t ld = 0;
     int32_t n = 0, link = 0, g = 1;
+    bool lazy = false;               // kFlagLazy: the step table fits the server's LDS
     size_t off = 0;                  // arena: matrix
     size_t rec_off = 0;              // records area
     size_t stage_off = 0;            // staging area (pageable input only)
@@ -280,7 +281,7 @@ bool admit(hac_server *s) {
             E.inst.n = J.n;
             E.inst.link = J.link;
             E.inst.exchange = 0;
-            E.inst.flags = 0;
+            E.inst.flags = J.lazy ? hac::kFlagLazy : 0;
             E.src = src;
             E.ld = ld;
             E.g = J.g;
@@ -429,10 +430,14 @@ int hac_server_create(hac_ctx *ctx, size_t hbm_budget_bytes, int32_t max_jobs, i
         free_server(s);
         return HAC_EDEVICE;
     }
-    // LDS per workgroup: enough for every job size up to max_n with its group.
+    // LDS per workgroup: enough for every job size up to max_n with its group,
+    // with the lazy mirror's step table where that fits.
     size_t lds = 0;
-    for (int n = 2; n <= max_n; ++n)
-        lds = std::max(lds, hac::lds_bytes(n, hac::own_rows(n, group_for(n, s->info.lds_max)), true));
+    for (int n = 2; n <= max_n; ++n) {
+        const int own = hac::own_rows(n, group_for(n, s->info.lds_max));
+        const size_t with = hac::lds_bytes(n, own, true, true);
+        lds = std::max(lds, s->info.lazy && with <= s->info.lds_max ? with : hac::lds_bytes(n, own, true));
+    }
     if (lds > s->info.lds_max) {
         free_server(s);
         return HAC_EINVAL;
@@ -562,6 +567,7 @@ int hac_submit(hac_server *s, const float *host_dist, int64_t ld, int32_t n, int
     J.n = n;
     J.link = linkage;
     J.g = g;
+    J.lazy = s->info.lazy && hac::lds_bytes(n, hac::own_rows(n, g), true, true) <= s->lds;
     J.lay = lay;
     J.rc = HAC_OK;
     J.result.clear();

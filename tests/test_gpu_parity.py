@@ -335,6 +335,40 @@ def test_batch_all_linkages(ctx, torch):
             assert _same(got, exps[k]), (block, group, k, n, int(links[k]), _diff(got, exps[k]))
 
 
+def test_batch_lazy_mirror(ctx, torch):
+    """The lazy mirror (the update writes only the survivor's row; each pair
+    is read from whichever of its rows was written last) against writing
+    both halves: identical records for every linkage, on one workgroup and on
+    groups, with n a multiple of four (16-byte row scans) and not; both equal
+    the oracle."""
+    import paper_1709_06816_amd as hac
+    ns = np.array([2100, 2051, 515, 512, 257, 130, 99, 64, 7, 2], np.int64)  # the first two get groups
+    links = np.array([0, 1, 2, 3, 4, 5, 3, 2, 1, 0], np.int32)
+    mats = [synth.batch_instance(int(n), 7300 + k) for k, n in enumerate(ns)]
+    mats[1] = synth.quantized_matrix(2051, 7301, levels=6)  # many ties
+    offs, total = synth.pack_offsets(ns)
+    packed = np.zeros(total, np.float32)
+    for k, m in enumerate(mats):
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+    t = torch.from_numpy(packed).cuda()
+    moff, _ = synth.merge_offsets(ns)
+    exps = [oracle.run_f32(m, int(links[k])) for k, m in enumerate(mats)]
+    try:
+        for block, group in [(1024, 1), (1024, 4), (256, 1)]:
+            got = {}
+            for lazy in (1, 0):
+                _say("batch lazy=%d block=%d group=%d" % (lazy, block, group))
+                ctx.set_option(hac.OPT_LAZY_MIRROR, lazy)
+                got[lazy], st = _batch_with_plan(ctx, torch, t, offs, ns, links, block, group)
+                assert st["group"] == group
+            assert _same(got[1], got[0]), (block, group)
+            for k in range(len(ns)):
+                n = int(ns[k])
+                assert _same(got[1][moff[k]:moff[k] + n - 1], exps[k]), (block, group, k, n)
+    finally:
+        ctx.set_option(hac.OPT_LAZY_MIRROR, 1)
+
+
 def _batch_with_plan(ctx, torch, t, offs, ns, links, block, group):
     import paper_1709_06816_amd as hac
     ctx.set_option(hac.OPT_BATCH_BLOCK, block)
