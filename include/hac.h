@@ -318,9 +318,11 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *   graph:             hac_batch: 0 = stream launches, 1 = an existing graph was
  *                      relaunched, 2 = a graph was built for this call; with a
  *                      graph kernel_ms covers upload, fills and kernel
- *   forced_rounds:     hac_run with deferred rescans: extra argmin rounds taken
- *                      because a row's lower bound won (see HAC_OPT_DEFER)
- *   deferred:          1 if the last hac_run deferred its rescans
+ *   forced_rounds:     with deferred rescans: extra argmin rounds taken because
+ *                      a row's lower bound won (see HAC_OPT_DEFER); hac_batch:
+ *                      summed over its instances
+ *   deferred:          1 if the last call deferred its rescans (hac_batch
+ *                      always does)
  *   rounds:            hac_run through rounds of merges (HAC_OPT_ROUNDS): rounds
  *                      run (0 otherwise)
  *   handed_over:       1 if those rounds stopped part-way (few merges per round:

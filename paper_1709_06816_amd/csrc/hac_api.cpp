@@ -1076,7 +1076,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->pending_plan_source = plan_source;
     c->pending_plan_share = B.group > 1 ? plan.share : 0;
     c->pending_graph = graphed;
-    c->pending_deferred = 0;
+    c->pending_deferred = 1;
     c->pending_rounds = false;
     c->pending_scan = false;
     return finish(c, s, count, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)rec_extent, flags, c->ws);

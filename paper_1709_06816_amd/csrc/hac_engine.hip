@@ -904,6 +904,9 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
 
 // One batch instance on workgroup w of a group of g (g = 1: the whole
 // instance on this workgroup), including its set-up.  Returns when done.
+// Deferred rescans: with the lazy mirror a rescan reads scattered entries, and
+// stale rows settled together in forced rounds cost less than rescanning at
+// every merge.
 template <int B>
 __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, Control *ctl,
                                uint64_t timeout, Stats &st, uint32_t epoch_base = 0) {
@@ -941,7 +944,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     }
     init_masks<B>(L, n);  // size1 shares space with the tile
     __syncthreads();
-    merge_loop<B, kLoopCached>(I, g, w, L, ctl, timeout, st, epoch0);
+    merge_loop<B, kLoopDefer>(I, g, w, L, ctl, timeout, st, epoch0);
 }
 
 // Batch: the first `ngroups` entries of `order` are run by fixed groups of

@@ -360,7 +360,7 @@ def test_batch_lazy_mirror(ctx, torch):
                 _say("batch lazy=%d block=%d group=%d" % (lazy, block, group))
                 ctx.set_option(hac.OPT_LAZY_MIRROR, lazy)
                 got[lazy], st = _batch_with_plan(ctx, torch, t, offs, ns, links, block, group)
-                assert st["group"] == group
+                assert st["group"] == group and st["deferred"] == 1
             assert _same(got[1], got[0]), (block, group)
             for k in range(len(ns)):
                 n = int(ns[k])
