@@ -444,7 +444,7 @@ float batch_try_plan(hac_ctx *c, float *scratch, const float *packed, int64_t ex
 // results never depend on the plan.  Coordinate search: first the threads
 // per workgroup with every instance on one workgroup (each block size
 // carries its own tile sizes: 8-deep update batches and 8-load rescan
-// segments per lane at 256 threads, 2 and 4 at 1024), then with that block
+// segments per lane at 256 threads, 4 and 4 at 1024), then with that block
 // size the workgroups per large instance (2, 4, 8) and how many of the
 // co-resident workgroups groups may take (a quarter, half, three quarters),
 // which decides how many of the largest instances get a group.  Plans whose

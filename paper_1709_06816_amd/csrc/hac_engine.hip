@@ -68,6 +68,10 @@ constexpr int kMaxWaves = 16;
 // loads per rescan step.  Large workgroups need fewer per thread for the same
 // bytes in flight and have only 128 VGPRs per thread.
 template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
+// The batch kernel's 1024-thread workgroups load four chunks per wave at once
+// (an n = 4096 instance's rows in one batch): measured faster there despite
+// some register spill, slower in the single-instance and serving kernels.
+template <int B> constexpr int batch_upd() { return B >= 1024 ? 4 : 8; }
 template <int B> constexpr int seg_unroll() { return B >= 1024 ? 4 : 8; }
 
 // 64-bit value of the lane picked by DPP control CTRL; lanes of rows outside
@@ -526,12 +530,11 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // its live rows, as Section 5.3 step 1 scans the whole matrix.
 enum : int { kLoopCached = 0, kLoopDefer = 1, kLoopScan = 2 };
 
-template <int B, int kMode>
+template <int B, int kMode, int U = upd_batch<B>()>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
                            uint64_t timeout, Stats &st, uint32_t epoch0, int s0 = 0, uint64_t *keys = nullptr,
                            int round0 = 0) {
     constexpr int W = B / 64;
-    constexpr int U = upd_batch<B>();
     constexpr bool scan = kMode == kLoopScan, defer = kMode == kLoopDefer;
     const int n = I.n, link = I.link;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
@@ -906,8 +909,8 @@ __global__ __launch_bounds__(B) void k_run(Instance I, Control *ctl, uint64_t ti
 // instance on this workgroup), including its set-up.  Returns when done.
 // Deferred rescans: with the lazy mirror a rescan reads scattered entries, and
 // stale rows settled together in forced rounds cost less than rescanning at
-// every merge.
-template <int B>
+// every merge.  U: update batch depth (chunks per wave loaded at once).
+template <int B, int U = upd_batch<B>()>
 __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, Control *ctl,
                                uint64_t timeout, Stats &st, uint32_t epoch_base = 0) {
     const int n = I.n;
@@ -944,7 +947,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     }
     init_masks<B>(L, n);  // size1 shares space with the tile
     __syncthreads();
-    merge_loop<B, kLoopDefer>(I, g, w, L, ctl, timeout, st, epoch0);
+    merge_loop<B, kLoopDefer, U>(I, g, w, L, ctl, timeout, st, epoch0);
 }
 
 // Batch: the first `ngroups` entries of `order` are run by fixed groups of
@@ -965,7 +968,7 @@ __global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
         const int base = gbase[t], g = gsize[t];
         if (wg >= base && wg < base + g) {
             const Instance I = insts[order[t]];
-            if (I.n > 1) batch_instance<B>(I, g, wg - base, smem, ctl, timeout, st);
+            if (I.n > 1) batch_instance<B, batch_upd<B>()>(I, g, wg - base, smem, ctl, timeout, st);
             __syncthreads();
         }
     }
@@ -976,7 +979,7 @@ __global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
         __syncthreads();
         if (q >= count) break;
         const Instance I = insts[order[q]];
-        if (I.n > 1) batch_instance<B>(I, 1, 0, smem, ctl, timeout, st);
+        if (I.n > 1) batch_instance<B, batch_upd<B>()>(I, 1, 0, smem, ctl, timeout, st);
         __syncthreads();
     }
     flush_stats<B>(ctl, st);
