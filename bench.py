@@ -277,7 +277,10 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps, cpu):
         kb.append(ctx.stats()["kernel_ms"])
     st = ctx.stats()
     ns64 = spec.ns.astype(np.float64)
-    alg = float(np.sum(4.0 * ns64 * (ns64 - 1.0))) + 16.0 * st["update_elems"] + 4.0 * st["rescan_elems"] \
+    # Set-up (read the upper triangle, write its mirror), then 12 B per updated
+    # entry (the batch kernel's lazy mirror reads D_ik, D_jk and writes D_ik
+    # only), 4 B per rescanned live entry and 16 B per record.
+    alg = float(np.sum(4.0 * ns64 * (ns64 - 1.0))) + 12.0 * st["update_elems"] + 4.0 * st["rescan_elems"] \
         + 16.0 * float(mtot)
     log("batch: per-instance loop")
     one_loop()
