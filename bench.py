@@ -301,7 +301,7 @@ def batch_leg(torch, hac, ctx, count, n_lo, n_hi, reps, cpu):
         "identical_to_loop": same, "merges": int(mtot), "alg_bytes": alg,
         "achieved_gbs": alg / (kbm / 1000.0) / 1e9, "frac_hbm_peak": alg / (kbm / 1000.0) / 1e9 / HBM_PEAK_GBS,
         "plan": {"block": st["block"], "group": st["group"], "workgroups": st["workgroups"], "graph": st["graph"],
-                 "share_quarters": st["plan_share"], "source": st["plan_source"]},
+                 "share_quarters": st["plan_share"], "update_chunks": st["plan_update"], "source": st["plan_source"]},
     }
     gold = golden("batch_1024")
     if gold is not None and count == gold["count"]:

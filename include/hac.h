@@ -224,15 +224,20 @@ const char *hac_last_error(const hac_ctx *ctx);
  *                        a scratch copy of the first batch of each size mix, and
  *                        caches the choice in the context (1 = on, the default;
  *                        0 = off): threads per workgroup (256 or 1024, each with
- *                        its own update and rescan tile sizes), then workgroups
- *                        per large instance (1, 2, 4, 8) and the share of the
- *                        co-resident workgroups the groups may take (a quarter,
- *                        half, three quarters: how many of the largest
- *                        instances get a group).  A candidate whose run reports
- *                        an error is never chosen.  Costs eleven extra runs of
- *                        that first batch; see hac_stats.plan_source.
+ *                        its own rescan tile size), then workgroups per large
+ *                        instance (1, 2, 4, 8) and the share of the co-resident
+ *                        workgroups the groups may take (a quarter, half, three
+ *                        quarters: how many of the largest instances get a
+ *                        group), then at 1024 threads the update tile (2 or 4
+ *                        column chunks per wave loaded at once).  A candidate
+ *                        whose run reports an error is never chosen.  Costs
+ *                        twelve extra runs of that first batch; see
+ *                        hac_stats.plan_source.
  *   HAC_OPT_BATCH_BLOCK  force hac_batch's threads per workgroup: 256 or 1024
  *   HAC_OPT_BATCH_GROUP  force hac_batch's workgroups per large instance (1..64)
+ *   HAC_OPT_BATCH_UPDATE force hac_batch's update tile at 1024 threads: 2 or 4
+ *                        column chunks per wave (0 = 4 when not tuned; 256
+ *                        threads always use 8)
  *   HAC_OPT_GRAPH        hac_batch enqueues its descriptor upload, fills and
  *                        kernel as one HIP graph, instantiated once per layout
  *                        (instance count, plan, workspace) and relaunched with
@@ -294,7 +299,8 @@ typedef enum {
     HAC_OPT_DEFER = 11,
     HAC_OPT_ROUNDS = 12,
     HAC_OPT_INJECT_STALL = 13,
-    HAC_OPT_LAZY_MIRROR = 14
+    HAC_OPT_LAZY_MIRROR = 14,
+    HAC_OPT_BATCH_UPDATE = 15
 } hac_option;
 int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
 
@@ -343,6 +349,8 @@ int hac_set_option(hac_ctx *ctx, int32_t option, int64_t value);
  *                      same size mix (cached in the context)
  *   plan_share:        hac_batch with groups: quarters of the co-resident
  *                      workgroups the groups were allowed to take (0 otherwise)
+ *   plan_update:       hac_batch: column chunks per wave in each update batch
+ *                      (8 at 256 threads; 2 or 4 at 1024)
  */
 typedef struct {
     double kernel_ms;
@@ -366,6 +374,7 @@ typedef struct {
     int64_t rounds_update_elems;
     int32_t plan_source;
     int32_t plan_share;
+    int32_t plan_update;
 } hac_stats;
 int hac_get_stats(const hac_ctx *ctx, hac_stats *out);
 

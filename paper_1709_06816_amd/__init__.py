@@ -41,6 +41,7 @@ OPT_DEFER = 11
 OPT_ROUNDS = 12
 OPT_INJECT_STALL = 13
 OPT_LAZY_MIRROR = 14
+OPT_BATCH_UPDATE = 15
 MAX_N = 65536
 MAX_BATCH_N = 8192
 NOALLOC_MAX_N = 65536
@@ -77,7 +78,7 @@ class _Stats(ctypes.Structure):
                 ("handed_over", ctypes.c_int32), ("compactions", ctypes.c_int32),
                 ("rounds_ms", ctypes.c_double), ("rounds_rescan_elems", ctypes.c_int64),
                 ("rounds_update_elems", ctypes.c_int64), ("plan_source", ctypes.c_int32),
-                ("plan_share", ctypes.c_int32)]
+                ("plan_share", ctypes.c_int32), ("plan_update", ctypes.c_int32)]
 
 
 PHASES = ("setup", "exchange", "update", "rescan", "candidates")

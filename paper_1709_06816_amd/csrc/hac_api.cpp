@@ -34,7 +34,11 @@ struct BatchPlan {
     int block = 256;  // threads per workgroup
     int group = 1;    // workgroups per large instance (1 = every instance on one workgroup)
     int share = 2;    // quarters of the co-resident workgroups that groups may take
+    int upd = 0;      // update tile at 1024 threads: 2 or 4 chunks per wave (0: 4)
 };
+
+// Update tile a plan runs with (the batch kernel's variants).
+int plan_update(const BatchPlan &p) { return p.block != 1024 ? 8 : p.upd == 2 ? 2 : 4; }
 
 }  // namespace
 
@@ -64,14 +68,14 @@ struct hac_ctx {
 
     hac_stats stats{};
     int64_t opt_wgs = 0, opt_single_n = 0, opt_timeout_ms = 0, opt_exchange = 0, opt_profile = 0;
-    int64_t opt_block = 0, opt_batch_block = 0, opt_batch_group = 0, opt_autotune = 1;
+    int64_t opt_block = 0, opt_batch_block = 0, opt_batch_group = 0, opt_batch_upd = 0, opt_autotune = 1;
     std::unordered_map<std::string, BatchPlan> plans;  // tuned batch plans by size mix
     int64_t opt_graph = 1;
     int64_t opt_defer = 1;
     int64_t opt_rounds = 1;
     int64_t opt_stall = 0;
     bool opt_lazy = true;  // HAC_OPT_LAZY_MIRROR
-    int pending_plan_source = 0, pending_plan_share = 0;  // hac_batch: where its plan came from
+    int pending_plan_source = 0, pending_plan_share = 0, pending_plan_upd = 0;  // hac_batch: its plan
     std::unordered_map<std::string, hipGraphExec_t> graphs;  // batch graphs by layout
 
     // State of the last enqueued call, for hac_sync / stats.
@@ -217,6 +221,7 @@ int check_status(hac_ctx *c) {
     c->stats.graph = c->pending_graph;
     c->stats.plan_source = c->pending_plan_source;
     c->stats.plan_share = c->pending_plan_share;
+    c->stats.plan_update = c->pending_plan_upd;
     if (c->pending_rounds && c->pending_count == 1 && (st[0] & hac::kHandover)) {
         // The round engine handed the rest of the merges to the kernel
         // queued behind it.
@@ -383,6 +388,7 @@ int batch_prepare(hac_ctx *c, float *base, const int64_t *offsets, const int32_t
     L.gsize = reinterpret_cast<int32_t *>(ws + gb_off) + ngroups;
     L.ngroups = ngroups;
     L.block = plan.block;
+    L.upd = plan_update(plan);
     L.grid = grid;
     L.lds = lds;
     B->st_off = st_off;
@@ -447,7 +453,9 @@ float batch_try_plan(hac_ctx *c, float *scratch, const float *packed, int64_t ex
 // segments per lane at 256 threads, 4 and 4 at 1024), then with that block
 // size the workgroups per large instance (2, 4, 8) and how many of the
 // co-resident workgroups groups may take (a quarter, half, three quarters),
-// which decides how many of the largest instances get a group.  Plans whose
+// which decides how many of the largest instances get a group, then at 1024
+// threads the other update tile (2 instead of 4 chunks per wave: fewer
+// registers, two load batches for the largest rows).  Plans whose
 // run reports an error are skipped; if every plan fails, the default plan is
 // kept and the real run reports the error.
 int batch_autotune(hac_ctx *c, float *packed, int64_t extent, const int64_t *offsets,
@@ -471,6 +479,11 @@ int batch_autotune(hac_ctx *c, float *packed, int64_t extent, const int64_t *off
     const int block = best->block;
     for (int group : {2, 4, 8})
         for (int share : {1, 2, 3}) consider(BatchPlan{block, group, share});
+    if (best->block == 1024) {
+        BatchPlan p = *best;
+        p.upd = 2;
+        consider(p);
+    }
     (void)hipStreamSynchronize(s);
     (void)hipFree(scratch);
     c->err.clear();
@@ -605,6 +618,11 @@ int hac_set_option(hac_ctx *c, int32_t option, int64_t value) {
     case HAC_OPT_BATCH_GROUP:
         if (value > 64) return fail(c, HAC_EINVAL, "batch group %lld > 64", (long long)value);
         c->opt_batch_group = value;
+        return HAC_OK;
+    case HAC_OPT_BATCH_UPDATE:
+        if (value != 0 && value != 2 && value != 4)
+            return fail(c, HAC_EINVAL, "batch update tile %lld is not 0, 2 or 4", (long long)value);
+        c->opt_batch_upd = value;
         return HAC_OK;
     case HAC_OPT_AUTOTUNE: c->opt_autotune = value != 0; return HAC_OK;
     case HAC_OPT_GRAPH: c->opt_graph = value != 0; return HAC_OK;
@@ -780,7 +798,7 @@ int run_rounds(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *o
     c->pending_block = hac::kRoundsBlock;
     c->pending_group = G;
     c->pending_graph = 0;
-    c->pending_plan_source = c->pending_plan_share = 0;
+    c->pending_plan_source = c->pending_plan_share = c->pending_plan_upd = 0;
     c->pending_deferred = 0;
     c->pending_rounds = true;
     c->pending_seq_wgs = g;
@@ -845,7 +863,7 @@ int run_scan(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     c->pending_block = hac::kScanBlock;
     c->pending_group = G;
     c->pending_graph = 0;
-    c->pending_plan_source = c->pending_plan_share = 0;
+    c->pending_plan_source = c->pending_plan_share = c->pending_plan_upd = 0;
     c->pending_deferred = 0;
     c->pending_scan = true;
     return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
@@ -943,7 +961,7 @@ int run_impl(hac_ctx *c, float *dist, int32_t n, int32_t linkage, hac_merge *out
     c->pending_block = block;
     c->pending_group = g;
     c->pending_graph = 0;
-    c->pending_plan_source = c->pending_plan_share = 0;
+    c->pending_plan_source = c->pending_plan_share = c->pending_plan_upd = 0;
     c->pending_deferred = (run_flags & hac::kFlagDefer) ? 1 : 0;
     if (noalloc) return finish(c, s, 1, nullptr, 0, flags, ws);
     return finish(c, s, 1, out, (flags & HAC_OUT_DEVICE) ? 0 : (size_t)(n - 1), flags, ws);
@@ -1020,9 +1038,10 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     // Plan: forced by options, cached for this size mix, or tuned now.
     BatchPlan plan;
     int plan_source = 0;  // 0: default or forced by options, 1: tuned now, 2: tuned earlier (cached)
-    if (c->opt_batch_block > 0 || c->opt_batch_group > 0) {
+    if (c->opt_batch_block > 0 || c->opt_batch_group > 0 || c->opt_batch_upd > 0) {
         if (c->opt_batch_block > 0) plan.block = (int)c->opt_batch_block;
         if (c->opt_batch_group > 0) plan.group = (int)c->opt_batch_group;
+        plan.upd = (int)c->opt_batch_upd;
     } else {
         const std::string sig = batch_signature(ns, linkages, count);
         auto it = c->plans.find(sig);
@@ -1048,7 +1067,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
         // pinned buffer at every launch.
         char key[256];
         snprintf(key, sizeof key, "%p:%zu:%zu:%zu:%zu:%d:%d:%d:%d:%zu:%llu", c->ws, B.in_off, B.up_bytes, B.st_off + B.st_bytes,
-                 B.sl_bytes, B.L.count, B.L.ngroups, B.L.block, B.L.grid, B.L.lds,
+                 B.sl_bytes, B.L.count, B.L.ngroups, B.L.block * 16 + B.L.upd, B.L.grid, B.L.lds,
                  (unsigned long long)timeout_ticks(c));
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -1075,6 +1094,7 @@ int hac_batch(hac_ctx *c, float *packed, const int64_t *offsets, const int32_t *
     c->pending_group = B.group;
     c->pending_plan_source = plan_source;
     c->pending_plan_share = B.group > 1 ? plan.share : 0;
+    c->pending_plan_upd = plan_update(plan);
     c->pending_graph = graphed;
     c->pending_deferred = 1;
     c->pending_rounds = false;

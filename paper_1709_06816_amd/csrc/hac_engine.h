@@ -129,6 +129,7 @@ struct BatchLaunch {
     const int32_t *gsize;
     int ngroups;
     int block;   // 256 or 1024 threads per workgroup
+    int upd;     // chunks per wave in each update batch: 8 at 256 threads, 2 or 4 at 1024
     int grid;    // workgroups (all co-resident)
     size_t lds;  // dynamic LDS per workgroup
 };

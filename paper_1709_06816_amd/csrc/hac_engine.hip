@@ -68,10 +68,6 @@ constexpr int kMaxWaves = 16;
 // loads per rescan step.  Large workgroups need fewer per thread for the same
 // bytes in flight and have only 128 VGPRs per thread.
 template <int B> constexpr int upd_batch() { return B >= 1024 ? 2 : 8; }
-// The batch kernel's 1024-thread workgroups load four chunks per wave at once
-// (an n = 4096 instance's rows in one batch): measured faster there despite
-// some register spill, slower in the single-instance and serving kernels.
-template <int B> constexpr int batch_upd() { return B >= 1024 ? 4 : 8; }
 template <int B> constexpr int seg_unroll() { return B >= 1024 ? 4 : 8; }
 
 // 64-bit value of the lane picked by DPP control CTRL; lanes of rows outside
@@ -954,8 +950,9 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
 // workgroups (task t on workgroups gbase[t] .. gbase[t]+gsize[t]-1); every
 // workgroup then takes the remaining entries one at a time from a queue
 // (largest instances first).  Launched cooperatively when ngroups > 0 so that
-// the members of a group are co-resident.
-template <int B>
+// the members of a group are co-resident.  U: chunks per wave in each update
+// batch (a plan parameter).
+template <int B, int U>
 __global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
                                              const int32_t *__restrict__ order, int count,
                                              const int32_t *__restrict__ gbase,
@@ -968,7 +965,7 @@ __global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
         const int base = gbase[t], g = gsize[t];
         if (wg >= base && wg < base + g) {
             const Instance I = insts[order[t]];
-            if (I.n > 1) batch_instance<B, batch_upd<B>()>(I, g, wg - base, smem, ctl, timeout, st);
+            if (I.n > 1) batch_instance<B, U>(I, g, wg - base, smem, ctl, timeout, st);
             __syncthreads();
         }
     }
@@ -979,7 +976,7 @@ __global__ __launch_bounds__(B) void k_batch(const Instance *__restrict__ insts,
         __syncthreads();
         if (q >= count) break;
         const Instance I = insts[order[q]];
-        if (I.n > 1) batch_instance<B, batch_upd<B>()>(I, 1, 0, smem, ctl, timeout, st);
+        if (I.n > 1) batch_instance<B, U>(I, 1, 0, smem, ctl, timeout, st);
         __syncthreads();
     }
     flush_stats<B>(ctl, st);
@@ -1247,8 +1244,9 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
                          run_kernel(1024, kLoopCached),  run_kernel(256, kLoopDefer),
                          run_kernel(512, kLoopDefer),    run_kernel(1024, kLoopDefer),
                          run_kernel(256, kLoopScan),     run_kernel(512, kLoopScan),
-                         run_kernel(1024, kLoopScan),    reinterpret_cast<const void *>(&k_batch<256>),
-                         reinterpret_cast<const void *>(&k_batch<1024>), reinterpret_cast<const void *>(&k_serve<256>),
+                         run_kernel(1024, kLoopScan),    reinterpret_cast<const void *>(&k_batch<256, 8>),
+                         reinterpret_cast<const void *>(&k_batch<1024, 2>),
+                         reinterpret_cast<const void *>(&k_batch<1024, 4>), reinterpret_cast<const void *>(&k_serve<256>),
                          reinterpret_cast<const void *>(&k_serve<1024>)};
     for (const void *fn : fns) {
         hipFuncAttributes a;
@@ -1266,15 +1264,19 @@ hipError_t engine_setup(size_t max_lds, size_t *usable) {
 }
 
 
-static const void *batch_kernel(int block) {
-    return block == 1024 ? reinterpret_cast<const void *>(&k_batch<1024>)
-                         : reinterpret_cast<const void *>(&k_batch<256>);
+// Batch kernel variants: 256 threads with 8-chunk update batches; 1024
+// threads with 2 or 4 (4 loads an n = 4096 instance's rows in one batch at
+// the cost of some register spill; the plan search picks).
+static const void *batch_kernel(int block, int upd) {
+    if (block != 1024) return reinterpret_cast<const void *>(&k_batch<256, 8>);
+    return upd == 2 ? reinterpret_cast<const void *>(&k_batch<1024, 2>)
+                    : reinterpret_cast<const void *>(&k_batch<1024, 4>);
 }
 
 int engine_occupancy(size_t lds, int block, bool batch, int32_t run_flags) {
     int blocks = 0;
     const int mode = (run_flags & kFlagScan) ? kLoopScan : (run_flags & kFlagDefer) ? kLoopDefer : kLoopCached;
-    const void *fn = batch ? batch_kernel(block) : run_kernel(block, mode);
+    const void *fn = batch ? batch_kernel(block, 4) : run_kernel(block, mode);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, block, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -1367,9 +1369,9 @@ hipError_t launch_batch(const BatchLaunch &b, Control *ctl, uint64_t timeout_tic
     uint64_t a7 = timeout_ticks;
     void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
     if (b.ngroups > 0)
-        return hipLaunchCooperativeKernel(batch_kernel(b.block), dim3(b.grid), dim3(b.block), args,
+        return hipLaunchCooperativeKernel(batch_kernel(b.block, b.upd), dim3(b.grid), dim3(b.block), args,
                                           (unsigned)b.lds, stream);
-    return hipLaunchKernel(batch_kernel(b.block), dim3(b.grid), dim3(b.block), args, b.lds, stream);
+    return hipLaunchKernel(batch_kernel(b.block, b.upd), dim3(b.grid), dim3(b.block), args, b.lds, stream);
 }
 
 static hipError_t add_zero_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *dep, size_t ndep,
@@ -1425,7 +1427,7 @@ hipError_t build_batch_graph(const BatchLaunch &b, Control *ctl, uint64_t timeou
         uint64_t a7 = timeout_ticks;
         void *args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
         hipKernelNodeParams kp{};
-        kp.func = const_cast<void *>(batch_kernel(b.block));
+        kp.func = const_cast<void *>(batch_kernel(b.block, b.upd));
         kp.gridDim = dim3(b.grid);
         kp.blockDim = dim3(b.block);
         kp.sharedMemBytes = (unsigned)b.lds;

@@ -369,16 +369,18 @@ def test_batch_lazy_mirror(ctx, torch):
         ctx.set_option(hac.OPT_LAZY_MIRROR, 1)
 
 
-def _batch_with_plan(ctx, torch, t, offs, ns, links, block, group):
+def _batch_with_plan(ctx, torch, t, offs, ns, links, block, group, upd=0):
     import paper_1709_06816_amd as hac
     ctx.set_option(hac.OPT_BATCH_BLOCK, block)
     ctx.set_option(hac.OPT_BATCH_GROUP, group)
+    ctx.set_option(hac.OPT_BATCH_UPDATE, upd)
     try:
         res = ctx.batch(t, offs, ns, links, preserve=True)
         return res, ctx.stats()
     finally:
         ctx.set_option(hac.OPT_BATCH_BLOCK, 0)
         ctx.set_option(hac.OPT_BATCH_GROUP, 0)
+        ctx.set_option(hac.OPT_BATCH_UPDATE, 0)
 
 
 def test_batch_plans_identical(ctx, torch):
@@ -395,11 +397,13 @@ def test_batch_plans_identical(ctx, torch):
         packed[offs[k]:offs[k] + m.size] = m.ravel()
     t = torch.from_numpy(packed).cuda()
     ref = None
-    for block, group in [(256, 1), (1024, 1), (256, 4), (1024, 8), (256, 16)]:
-        _say("batch plan block=%d group=%d" % (block, group))
-        res, st = _batch_with_plan(ctx, torch, t, offs, ns, spec.linkages, block, group)
+    for block, group, upd in [(256, 1, 0), (1024, 1, 0), (1024, 1, 2), (256, 4, 0), (1024, 8, 0), (1024, 2, 2),
+                              (256, 16, 0)]:
+        _say("batch plan block=%d group=%d update=%d" % (block, group, upd))
+        res, st = _batch_with_plan(ctx, torch, t, offs, ns, spec.linkages, block, group, upd)
         assert st["block"] == block
         assert st["group"] == group
+        assert st["plan_update"] == (8 if block == 256 else upd or 4)
         if ref is None:
             ref = res
         else:
@@ -409,6 +413,7 @@ def test_batch_plans_identical(ctx, torch):
     assert _same(res, ref)
     st = ctx.stats()
     assert st["block"] in (256, 1024) and st["plan_source"] == 1
+    assert st["plan_update"] in ((8,) if st["block"] == 256 else (2, 4))
     assert st["plan_share"] in ((1, 2, 3) if st["group"] > 1 else (0,))
     res = ctx.batch(t, offs, ns, spec.linkages, preserve=True)  # cached plan
     assert _same(res, ref)
