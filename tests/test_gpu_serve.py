@@ -104,6 +104,23 @@ def test_server_matches_run_and_oracle(ctx, torch, hac):
         _say("stats", st)
 
 
+def test_server_without_lazy_mirror(ctx, torch, hac):
+    """A server created with HAC_OPT_LAZY_MIRROR = 0 (every update writes
+    both halves, as a job whose step table does not fit the LDS does): the
+    same records as hac_run."""
+    jobs = _jobs()
+    refs = [_run_ref(ctx, torch, d, l) for n, l, d in jobs]
+    ctx.set_option(hac.OPT_LAZY_MIRROR, 0)
+    try:
+        with hac.Server(ctx, budget_bytes=1 << 30, max_jobs=64, max_n=8192) as srv:
+            tickets = {k: srv.submit(np.ascontiguousarray(d), l) for k, (n, l, d) in enumerate(jobs)}
+            got = _drain(srv, tickets)
+    finally:
+        ctx.set_option(hac.OPT_LAZY_MIRROR, 1)
+    for k, (n, l, d) in enumerate(jobs):
+        assert got[k].tobytes() == refs[k].tobytes(), (n, l)
+
+
 def test_server_mix_matches_run(ctx, torch, hac):
     """160 jobs submitted at once (n log-uniform on [64, 6000], all linkages,
     about a fifth of them on groups of two workgroups) from page-locked
