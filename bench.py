@@ -1,7 +1,7 @@
 """Benchmark of the Lance-Williams clustering library on one MI355X.
 
 Prints one JSON line.  The headline is the n=32768 RMSD-like complete-linkage
-dendrogram (BASELINE workload 3) through the default path of hac_run (rounds
+dendrogram through the default path of hac_run (rounds
 of reciprocal-nearest-neighbour merges, the tail handed to the
 one-merge-per-step kernel); a step is one hac_run over the whole instance
 (set-up, all 32767 merges, records sorted into merge order in device memory)
