@@ -13,16 +13,20 @@
 //             may each get a fixed group of workgroups (exchanging through
 //             their own slots), the rest take one workgroup each, largest
 //             first, from a queue; each workgroup does its instance's set-up
-//             itself.
+//             itself (deferred rescans, lazy mirror).
 //   k_serve   a persistent server: workgroups take jobs that the host
 //             publishes in a ring in host memory, one workgroup or a group per
-//             job, until the host stops it.
+//             job, until the host stops it (deferred rescans, lazy mirror where
+//             the job's step table fits the LDS).
 //
 // Data layout (one GPU, the whole matrix in HBM):
-//   * The n x n fp32 matrix is kept fully symmetric, row-major, so that both
-//     D[i][k] and D[k][i] of the merged row/column are reachable with
-//     coalesced row accesses (Section 5.2 stores only the upper half, split
-//     over processors; here both halves live in one HBM).
+//   * The n x n fp32 matrix is made fully symmetric, row-major, by the set-up,
+//     so that both D[i][k] and D[k][i] of the merged row/column are reachable
+//     with coalesced row accesses (Section 5.2 stores only the upper half,
+//     split over processors; here both halves live in one HBM).  k_run keeps
+//     it symmetric; the batch and serving kernels write only the survivor's
+//     row (lazy mirror: a pair is read from whichever of its two rows was
+//     written later, see pair_at).
 //   * Rows are owned in chunks of 64 by the group's workgroups (boustrophedon
 //     order over rounds of g chunks).  Each workgroup keeps, in LDS, a cache
 //     entry per owned row k: ord(min_{l>k live} D[k][l]) : 32 | argmin l : 16
@@ -36,11 +40,11 @@
 //            same on every workgroup, so no second broadcast is needed
 //            (steps 2-5 of Section 5.3).
 //   update   the owner of column k reads D[i][k], D[j][k] (row reads),
-//            applies the Table 1 update, writes D[i][k] (row) and D[k][i]
-//            (column, through symmetric storage) and refreshes its cache
-//            entry for row k; a row whose cached partner was i or j is
-//            rescanned at once or, deferred, keeps a lower bound (step 6;
-//            see merge_loop).
+//            applies the Table 1 update, writes D[i][k] (row) and, without
+//            the lazy mirror, D[k][i] (column, through symmetric storage),
+//            and refreshes its cache entry for row k; a row whose cached
+//            partner was i or j is rescanned at once or, deferred, keeps a
+//            lower bound (step 6; see merge_loop).
 //   row i    its new minimum over l > i is reduced from the new values
 //            themselves and carried in the next exchange.
 // Exchange between workgroups: each workgroup writes three 64-bit words
