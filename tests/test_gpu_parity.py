@@ -369,6 +369,35 @@ def test_batch_lazy_mirror(ctx, torch):
         ctx.set_option(hac.OPT_LAZY_MIRROR, 1)
 
 
+def test_batch_largest_instances(ctx, torch):
+    """Instances of the batch's largest size (HAC_MAX_BATCH_N = 8192, the
+    most LDS the lazy mirror's step table needs on one workgroup) beside
+    small ones, with and without the lazy mirror and on one workgroup and
+    on groups: each equals hac_run on the same matrix."""
+    import paper_1709_06816_amd as hac
+    ns = np.array([8192, 8191, 300, 5, 2], np.int64)
+    links = np.array([1, 3, 2, 0, 4], np.int32)
+    mats = [synth.batch_instance(int(n), 8800 + k) for k, n in enumerate(ns)]
+    offs, total = synth.pack_offsets(ns)
+    packed = np.zeros(total, np.float32)
+    for k, m in enumerate(mats):
+        packed[offs[k]:offs[k] + m.size] = m.ravel()
+    t = torch.from_numpy(packed).cuda()
+    moff, _ = synth.merge_offsets(ns)
+    refs = [_gpu_run(ctx, torch, m, int(links[k])) for k, m in enumerate(mats)]
+    try:
+        for lazy in (1, 0):
+            ctx.set_option(hac.OPT_LAZY_MIRROR, lazy)
+            for block, group in [(1024, 1), (1024, 4)]:
+                _say("batch largest lazy=%d block=%d group=%d" % (lazy, block, group))
+                res, st = _batch_with_plan(ctx, torch, t, offs, ns, links, block, group)
+                for k in range(len(ns)):
+                    n = int(ns[k])
+                    assert _same(res[moff[k]:moff[k] + n - 1], refs[k]), (lazy, block, group, k, n)
+    finally:
+        ctx.set_option(hac.OPT_LAZY_MIRROR, 1)
+
+
 def _batch_with_plan(ctx, torch, t, offs, ns, links, block, group, upd=0):
     import paper_1709_06816_amd as hac
     ctx.set_option(hac.OPT_BATCH_BLOCK, block)
