@@ -110,3 +110,14 @@ def test_linkage_names_match_header():
     body = re.search(r"typedef enum \{(.*?)\} hac_linkage;", src, re.S).group(1)
     declared = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"HAC_(\w+)\s*=\s*(\d+)", body)}
     assert declared == hac.LINKAGES
+
+
+def test_option_numbers_match_header():
+    """Every hac_option of include/hac.h has the binding's OPT_* constant of
+    the same name and value, and the binding defines no other."""
+    with open(os.path.join(ROOT, "include", "hac.h")) as f:
+        src = f.read()
+    body = re.search(r"typedef enum \{(.*?)\} hac_option;", src, re.S).group(1)
+    declared = {m.group(1): int(m.group(2)) for m in re.finditer(r"HAC_OPT_(\w+)\s*=\s*(\d+)", body)}
+    bound = {k[len("OPT_"):]: v for k, v in vars(hac).items() if k.startswith("OPT_") and isinstance(v, int)}
+    assert declared == bound
