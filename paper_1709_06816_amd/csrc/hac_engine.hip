@@ -132,6 +132,7 @@ __shared__ uint64_t s_red[2][kMaxWaves];
 // the survivor's row, [2] and [3] the same minima over the whole group.
 __shared__ uint64_t s_acc[2][4];
 __shared__ uint32_t s_nresc;
+__shared__ uint64_t s_lim;
 __shared__ uint32_t s_fail;
 __shared__ int s_inst;
 
@@ -593,9 +594,31 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         while (defer && (uint32_t)(win >> 32) != kEmptyOrd && (win & 0xFFFFull) == 0) {
             __syncthreads();  // p1, p2 are read; s_acc[b ^ 1] is clear; s_nresc is 0
             if (tid == 0 && i_prev >= 0 && owner_of_row(i_prev, g) == w) L.cache[local_of_row(i_prev, g)] = ip_entry;
+            // A workgroup alone settles only the stale rows whose bound key is
+            // not above its smallest exact key: the others cannot win the
+            // argmin that follows (that exact key is still there), and a
+            // forced round costs it no exchange, so later ones are cheap.
+            // Groups settle every stale row: fewer rows per round there meant
+            // many more forced rounds, each an exchange (measured slower).
+            uint64_t lim = kEmpty;
+            if (g == 1) {
+                if (tid == 0) s_lim = kEmpty;
+                __syncthreads();  // also orders row i_prev's entry above before the pass
+                uint64_t ex = kEmpty;
+                for (int li = tid; li < own_ch * 64; li += B) {
+                    const int k = row_of_local(li, g, w);
+                    const uint64_t c = L.cache[li];
+                    if (k < n && !(c & kStale) && (uint32_t)(c >> 32) != kEmptyOrd)
+                        ex = umin64(ex, (c & kHi32) | ((uint64_t)k << 16) | ((c >> 16) & 0xFFFFull));
+                }
+                lds_min(&s_lim, ex);
+                __syncthreads();
+                lim = s_lim;
+            }
             for (int li = tid; li < own_ch * 64; li += B) {
                 const int k = row_of_local(li, g, w);
-                if (k < n && k != i_prev && (L.cache[li] & kStale)) {
+                if (k < n && k != i_prev && (L.cache[li] & kStale) &&
+                    (((L.cache[li] & kHi32) | ((uint64_t)k << 16)) <= lim)) {
                     L.cache[li] = kEmptyRow;
                     L.rlist[atomicAdd(&s_nresc, 1u)] = (uint16_t)li;
                 }
