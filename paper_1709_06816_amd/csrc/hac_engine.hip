@@ -531,7 +531,7 @@ __device__ void fold_candidates(const Lds &L, int n, int g, int w, int own_ch, i
 // its live rows, as Section 5.3 step 1 scans the whole matrix.
 enum : int { kLoopCached = 0, kLoopDefer = 1, kLoopScan = 2 };
 
-template <int B, int kMode, int U = upd_batch<B>()>
+template <int B, int kMode, int U = upd_batch<B>(), bool kSoloLimit = false>
 __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Control *ctl,
                            uint64_t timeout, Stats &st, uint32_t epoch0, int s0 = 0, uint64_t *keys = nullptr,
                            int round0 = 0) {
@@ -594,14 +594,15 @@ __device__ void merge_loop(const Instance &I, int g, int w, const Lds &L, Contro
         while (defer && (uint32_t)(win >> 32) != kEmptyOrd && (win & 0xFFFFull) == 0) {
             __syncthreads();  // p1, p2 are read; s_acc[b ^ 1] is clear; s_nresc is 0
             if (tid == 0 && i_prev >= 0 && owner_of_row(i_prev, g) == w) L.cache[local_of_row(i_prev, g)] = ip_entry;
-            // A workgroup alone settles only the stale rows whose bound key is
-            // not above its smallest exact key: the others cannot win the
-            // argmin that follows (that exact key is still there), and a
-            // forced round costs it no exchange, so later ones are cheap.
-            // Groups settle every stale row: fewer rows per round there meant
-            // many more forced rounds, each an exchange (measured slower).
+            // In the batch and serving kernels (kSoloLimit) a workgroup alone
+            // settles only the stale rows whose bound key is not above its
+            // smallest exact key: the others cannot win the argmin that
+            // follows (that exact key is still there), and a forced round
+            // costs it no exchange, so later ones are cheap.  Groups settle
+            // every stale row: fewer rows per round there meant many more
+            // forced rounds, each an exchange (measured slower).
             uint64_t lim = kEmpty;
-            if (g == 1) {
+            if (kSoloLimit && g == 1) {
                 if (tid == 0) s_lim = kEmpty;
                 __syncthreads();  // also orders row i_prev's entry above before the pass
                 uint64_t ex = kEmpty;
@@ -970,7 +971,7 @@ __device__ void batch_instance(const Instance &I, int g, int w, uint8_t *smem, C
     }
     init_masks<B>(L, n);  // size1 shares space with the tile
     __syncthreads();
-    merge_loop<B, kLoopDefer, U>(I, g, w, L, ctl, timeout, st, epoch0);
+    merge_loop<B, kLoopDefer, U, true>(I, g, w, L, ctl, timeout, st, epoch0);
 }
 
 // Batch: the first `ngroups` entries of `order` are run by fixed groups of
